@@ -1,0 +1,261 @@
+/*
+ * FP64 reference time stepper for the fictitious-wave-domain Maxwell
+ * equations (oracle; TEST INFRASTRUCTURE ONLY, never linked into the
+ * product library).
+ *
+ * Plain loops in the order of the paper's Algorithm 1, one operation per
+ * loop nest, no tiling or fusion:
+ *   curl H with CPML memory variables (Section 3.4 / 3.1, eqs. HFD2)
+ *   inject the electric dipole current J^{n+1/2}
+ *   update E:   E^{n+1} = E^n + dt eps^-1 (curl H - J)      (Section 3.1)
+ *   record E^{n+1} and H^{n+1/2} at the receivers and add them to the
+ *   running DTFT with exp(i omega' t) at each field's own time stamp
+ *                                                             (Section 3.5)
+ *   curl E with CPML memory variables (eqs. HFD1)
+ *   update H:   H^{n+3/2} = H^{n+1/2} - dt mu^-1 curl E       (Section 3.1)
+ * OpenMP over the slowest (z) index only.
+ *
+ * Layout: every 3D array is [n3][n2][n1], x fastest (Section 3.8).
+ * Staggering: E1 (i+1/2,j,k), E2 (i,j+1/2,k), E3 (i,j,k+1/2),
+ *             H1 (i,j+1/2,k+1/2), H2 (i+1/2,j,k+1/2), H3 (i+1/2,j+1/2,k).
+ * D- at integer node i: sum_m cm[i][m] v[i-r+m]      (half nodes i-r..i+r-1)
+ * D+ at half node i+1/2: sum_m cp[i][m] u[i-r+1+m]   (nodes i-r+1..i+r)
+ * Only cells with every index in [r, n-1-r] are updated; the rest stay 0.
+ * CPML memory variables exist where an index is < nb or > n-1-nb on the
+ * derivative's own axis (the slab test of Section 3.4); they are stored
+ * full-size here for plainness.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int n1, n2, n3;            /* padded sizes */
+    int r, nb, nt;
+    double ch;                 /* dt / mu0 */
+    const double *ce1, *ce2, *ce3;     /* dt / eps at E1/E2/E3 positions */
+    const double *cm1, *cm2, *cm3;     /* D- tables [n_d][2r] */
+    const double *cp1, *cp2, *cp3;     /* D+ tables [n_d][2r] */
+    const double *a1i, *b1i, *a2i, *b2i, *a3i, *b3i;   /* CPML at integer nodes */
+    const double *a1h, *b1h, *a2h, *b2h, *a3h, *b3h;   /* CPML at half nodes */
+    /* source: component 0..2 (E1..E3 grid), base index, (2r)^3 moment*w/V */
+    int src_comp;
+    int src_base[3];
+    const double *src_q;       /* [2r][2r][2r] (z, y, x) */
+    const double *wavelet;     /* s_n, n = 0..nt-1 */
+    /* receivers: nrec x nchan stencils */
+    int nrec, nchan;
+    const int *chan;           /* [nchan] channel ids 0..5 = Ex..Hz */
+    const int *rec_base;       /* [nrec][nchan][3] */
+    const double *rec_w;       /* [nrec][nchan][2r][2r][2r] (z, y, x) */
+    int nfreq;
+    const double *phE_re, *phE_im;   /* [nt][nfreq] exp(i w' (n+1) dt) */
+    const double *phH_re, *phH_im;   /* [nt][nfreq] exp(i w' (n+1/2) dt) */
+    double *acc_re, *acc_im;   /* [nrec][nchan][nfreq] out */
+    int nthreads;
+} oracle_params;
+
+#define IDX(k, j, i) (((size_t)(k) * n2 + (size_t)(j)) * n1 + (size_t)(i))
+
+static int in_slab(int i, int n, int nb) { return i < nb || i > n - 1 - nb; }
+
+/* curl H at the E positions, CPML applied (Section 3.4 memory variables) */
+static void curl_h(const oracle_params *p, const double *H1, const double *H2,
+                   const double *H3, double *c1, double *c2, double *c3,
+                   double *mD2H3, double *mD3H2, double *mD3H1,
+                   double *mD1H3, double *mD1H2, double *mD2H1)
+{
+    const int n1 = p->n1, n2 = p->n2, n3 = p->n3, r = p->r, nb = p->nb;
+#pragma omp parallel for num_threads(p->nthreads) schedule(static)
+    for (int k = r; k <= n3 - 1 - r; k++) {
+        for (int j = r; j <= n2 - 1 - r; j++) {
+            for (int i = r; i <= n1 - 1 - r; i++) {
+                double D2H3 = 0, D3H2 = 0, D3H1 = 0, D1H3 = 0, D1H2 = 0, D2H1 = 0;
+                for (int m = 0; m < 2 * r; m++) {
+                    D2H3 += p->cm2[j * 2 * r + m] * H3[IDX(k, j - r + m, i)];
+                    D2H1 += p->cm2[j * 2 * r + m] * H1[IDX(k, j - r + m, i)];
+                    D3H2 += p->cm3[k * 2 * r + m] * H2[IDX(k - r + m, j, i)];
+                    D3H1 += p->cm3[k * 2 * r + m] * H1[IDX(k - r + m, j, i)];
+                    D1H3 += p->cm1[i * 2 * r + m] * H3[IDX(k, j, i - r + m)];
+                    D1H2 += p->cm1[i * 2 * r + m] * H2[IDX(k, j, i - r + m)];
+                }
+                size_t id = IDX(k, j, i);
+                if (in_slab(i, n1, nb)) {
+                    mD1H3[id] = p->b1i[i] * mD1H3[id] + p->a1i[i] * D1H3;
+                    mD1H2[id] = p->b1i[i] * mD1H2[id] + p->a1i[i] * D1H2;
+                    D1H3 += mD1H3[id];
+                    D1H2 += mD1H2[id];
+                }
+                if (in_slab(j, n2, nb)) {
+                    mD2H3[id] = p->b2i[j] * mD2H3[id] + p->a2i[j] * D2H3;
+                    mD2H1[id] = p->b2i[j] * mD2H1[id] + p->a2i[j] * D2H1;
+                    D2H3 += mD2H3[id];
+                    D2H1 += mD2H1[id];
+                }
+                if (in_slab(k, n3, nb)) {
+                    mD3H2[id] = p->b3i[k] * mD3H2[id] + p->a3i[k] * D3H2;
+                    mD3H1[id] = p->b3i[k] * mD3H1[id] + p->a3i[k] * D3H1;
+                    D3H2 += mD3H2[id];
+                    D3H1 += mD3H1[id];
+                }
+                c1[id] = D2H3 - D3H2;
+                c2[id] = D3H1 - D1H3;
+                c3[id] = D1H2 - D2H1;
+            }
+        }
+    }
+}
+
+/* curl E at the H positions, CPML applied */
+static void curl_e(const oracle_params *p, const double *E1, const double *E2,
+                   const double *E3, double *c1, double *c2, double *c3,
+                   double *mD2E3, double *mD3E2, double *mD3E1,
+                   double *mD1E3, double *mD1E2, double *mD2E1)
+{
+    const int n1 = p->n1, n2 = p->n2, n3 = p->n3, r = p->r, nb = p->nb;
+#pragma omp parallel for num_threads(p->nthreads) schedule(static)
+    for (int k = r; k <= n3 - 1 - r; k++) {
+        for (int j = r; j <= n2 - 1 - r; j++) {
+            for (int i = r; i <= n1 - 1 - r; i++) {
+                double D2E3 = 0, D3E2 = 0, D3E1 = 0, D1E3 = 0, D1E2 = 0, D2E1 = 0;
+                for (int m = 0; m < 2 * r; m++) {
+                    D2E3 += p->cp2[j * 2 * r + m] * E3[IDX(k, j - r + 1 + m, i)];
+                    D2E1 += p->cp2[j * 2 * r + m] * E1[IDX(k, j - r + 1 + m, i)];
+                    D3E2 += p->cp3[k * 2 * r + m] * E2[IDX(k - r + 1 + m, j, i)];
+                    D3E1 += p->cp3[k * 2 * r + m] * E1[IDX(k - r + 1 + m, j, i)];
+                    D1E3 += p->cp1[i * 2 * r + m] * E3[IDX(k, j, i - r + 1 + m)];
+                    D1E2 += p->cp1[i * 2 * r + m] * E2[IDX(k, j, i - r + 1 + m)];
+                }
+                size_t id = IDX(k, j, i);
+                if (in_slab(i, n1, nb)) {
+                    mD1E3[id] = p->b1h[i] * mD1E3[id] + p->a1h[i] * D1E3;
+                    mD1E2[id] = p->b1h[i] * mD1E2[id] + p->a1h[i] * D1E2;
+                    D1E3 += mD1E3[id];
+                    D1E2 += mD1E2[id];
+                }
+                if (in_slab(j, n2, nb)) {
+                    mD2E3[id] = p->b2h[j] * mD2E3[id] + p->a2h[j] * D2E3;
+                    mD2E1[id] = p->b2h[j] * mD2E1[id] + p->a2h[j] * D2E1;
+                    D2E3 += mD2E3[id];
+                    D2E1 += mD2E1[id];
+                }
+                if (in_slab(k, n3, nb)) {
+                    mD3E2[id] = p->b3h[k] * mD3E2[id] + p->a3h[k] * D3E2;
+                    mD3E1[id] = p->b3h[k] * mD3E1[id] + p->a3h[k] * D3E1;
+                    D3E2 += mD3E2[id];
+                    D3E1 += mD3E1[id];
+                }
+                c1[id] = D2E3 - D3E2;
+                c2[id] = D3E1 - D1E3;
+                c3[id] = D1E2 - D2E1;
+            }
+        }
+    }
+}
+
+static void update(const oracle_params *p, double *F, const double *coef,
+                   double scalar, const double *curl, double sign)
+{
+    const int n1 = p->n1, n2 = p->n2, n3 = p->n3, r = p->r;
+#pragma omp parallel for num_threads(p->nthreads) schedule(static)
+    for (int k = r; k <= n3 - 1 - r; k++)
+        for (int j = r; j <= n2 - 1 - r; j++)
+            for (int i = r; i <= n1 - 1 - r; i++) {
+                size_t id = IDX(k, j, i);
+                double c = coef ? coef[id] : scalar;
+                F[id] += sign * c * curl[id];
+            }
+}
+
+static double gather(const oracle_params *p, const double *F, const int *base,
+                     const double *w)
+{
+    const int n1 = p->n1, n2 = p->n2, L = 2 * p->r;
+    double u = 0.0;
+    for (int c = 0; c < L; c++)
+        for (int b = 0; b < L; b++)
+            for (int a = 0; a < L; a++)
+                u += w[(c * L + b) * L + a] *
+                     F[IDX(base[2] + c, base[1] + b, base[0] + a)];
+    return u;
+}
+
+/* Run nt steps from zero fields; accumulate the receiver DTFT. Returns 0, or
+ * 1 if any accumulator is non-finite, or -1 on allocation failure. */
+int oracle_run(const oracle_params *p)
+{
+    const int n1 = p->n1, n2 = p->n2, n3 = p->n3, L = 2 * p->r;
+    const size_t N = (size_t)n1 * n2 * n3;
+    const int nf = p->nfreq;
+    /* 6 fields, 6 curls, 12 CPML memory variables */
+    double *buf = calloc(24 * N, sizeof(double));
+    if (!buf) return -1;
+    double *E1 = buf, *E2 = buf + N, *E3 = buf + 2 * N;
+    double *H1 = buf + 3 * N, *H2 = buf + 4 * N, *H3 = buf + 5 * N;
+    double *c1 = buf + 6 * N, *c2 = buf + 7 * N, *c3 = buf + 8 * N;
+    double *m = buf + 9 * N;  /* m[0..5]: curl-H memories, m[6..11]: curl-E */
+    double *E[3] = {E1, E2, E3}, *H[3] = {H1, H2, H3}, *cH[3] = {c1, c2, c3};
+    memset(p->acc_re, 0, sizeof(double) * p->nrec * p->nchan * nf);
+    memset(p->acc_im, 0, sizeof(double) * p->nrec * p->nchan * nf);
+
+    for (int n = 0; n < p->nt; n++) {
+        curl_h(p, H1, H2, H3, c1, c2, c3, m, m + N, m + 2 * N, m + 3 * N,
+               m + 4 * N, m + 5 * N);
+        /* inject: curl H - J at the (2r)^3 support of the source component */
+        {
+            double *cc = cH[p->src_comp];
+            const int *b = p->src_base;
+            for (int c = 0; c < L; c++)
+                for (int bb = 0; bb < L; bb++)
+                    for (int a = 0; a < L; a++)
+                        cc[IDX(b[2] + c, b[1] + bb, b[0] + a)] -=
+                            p->wavelet[n] * p->src_q[(c * L + bb) * L + a];
+        }
+        update(p, E1, p->ce1, 0.0, c1, 1.0);
+        update(p, E2, p->ce2, 0.0, c2, 1.0);
+        update(p, E3, p->ce3, 0.0, c3, 1.0);
+        /* record E^{n+1} (stamp (n+1) dt) and H^{n+1/2} (stamp (n+1/2) dt) */
+        for (int ir = 0; ir < p->nrec; ir++)
+            for (int ic = 0; ic < p->nchan; ic++) {
+                int ch = p->chan[ic];
+                size_t s = (size_t)ir * p->nchan + ic;
+                const double *F = ch < 3 ? E[ch] : H[ch - 3];
+                double u = gather(p, F, p->rec_base + 3 * s, p->rec_w + s * L * L * L);
+                const double *pr = ch < 3 ? p->phE_re : p->phH_re;
+                const double *pi = ch < 3 ? p->phE_im : p->phH_im;
+                for (int f = 0; f < nf; f++) {
+                    p->acc_re[s * nf + f] += u * pr[(size_t)n * nf + f];
+                    p->acc_im[s * nf + f] += u * pi[(size_t)n * nf + f];
+                }
+            }
+        curl_e(p, E1, E2, E3, c1, c2, c3, m + 6 * N, m + 7 * N, m + 8 * N,
+               m + 9 * N, m + 10 * N, m + 11 * N);
+        update(p, H1, NULL, p->ch, c1, -1.0);
+        update(p, H2, NULL, p->ch, c2, -1.0);
+        update(p, H3, NULL, p->ch, c3, -1.0);
+    }
+    free(buf);
+    for (size_t s = 0; s < (size_t)p->nrec * p->nchan * nf; s++)
+        if (!isfinite(p->acc_re[s]) || !isfinite(p->acc_im[s])) return 1;
+    return 0;
+}
+
+/* One curl evaluation on given fields (no CPML state carried): used by the
+ * plane-wave symbol tests to pin the stencil offsets of the stepper itself. */
+void oracle_curl_h(const oracle_params *p, const double *H1, const double *H2,
+                   const double *H3, double *c1, double *c2, double *c3)
+{
+    size_t N = (size_t)p->n1 * p->n2 * p->n3;
+    double *m = calloc(6 * N, sizeof(double));
+    curl_h(p, H1, H2, H3, c1, c2, c3, m, m + N, m + 2 * N, m + 3 * N, m + 4 * N, m + 5 * N);
+    free(m);
+}
+
+void oracle_curl_e(const oracle_params *p, const double *E1, const double *E2,
+                   const double *E3, double *c1, double *c2, double *c3)
+{
+    size_t N = (size_t)p->n1 * p->n2 * p->n3;
+    double *m = calloc(6 * N, sizeof(double));
+    curl_e(p, E1, E2, E3, c1, c2, c3, m, m + N, m + 2 * N, m + 3 * N, m + 4 * N, m + 5 * N);
+    free(m);
+}
