@@ -1,0 +1,130 @@
+"""Benchmark of the FDTD hot path on one MI355X.
+
+A step is one full forward modelling of the marine layered workload
+(128 x 128 x 96 nodes, 162 x 162 x 130 padded cells, 3 frequencies,
+101 receivers x 6 channels, one x-dipole): per-forward set-up, every time
+step (E step with injection and H-channel DTFT, H step with E-channel DTFT)
+and the Green's-function normalisation.  The model is created (and its
+arrays uploaded) before the timed region.
+
+Prints one JSON line: Gcell.step/s (padded cells x time steps / wall time),
+the roofline of the dominant kernel (E step: algorithmic bytes / average
+kernel duration from HIP events recorded around every launch in the timed
+region), and the FP64 oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# HBM traffic of one E-step launch measured with rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE on this workload, scaled by the copy-kernel calibration;
+# None until measured for the current kernel.
+E_STEP_TRAFFIC_BYTES = None
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, nt_sample: int):
+    from oracle import forward as F
+    threads = min(16, os.cpu_count() or 1)
+    F.forward(w, threads=threads, nt=2)       # load + warm
+    t = time.perf_counter()
+    F.forward(w, threads=threads, nt=nt_sample)
+    dt = time.perf_counter() - t
+    cells = w.padded_cells
+    return {"value": cells * nt_sample / dt / 1e9, "unit": "Gcell*step/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{w.name}, first {nt_sample} time steps, FP64 C/OpenMP oracle, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by "
+              "source with no communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2304_00233_amd import emm
+    from workloads import configs
+
+    w = configs.marine_layered()
+    nt = 0
+    gold = os.path.join(ROOT, "tests", "golden", "marine_layered_oracle.json")
+    if os.path.exists(gold):
+        nt = json.load(open(gold))["nt"]
+    w = w.with_(nt=nt)
+    log(f"[bench] workload {w.name} padded cells {w.padded_cells}")
+
+    model = emm.Model(w, profile=1)
+    for i in range(args.warmup):
+        model.forward()
+        log(f"[bench] warmup {i} done")
+    e_ms = h_ms = 0.0
+    e_n = h_n = 0
+    dev_ms = 0.0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        model.forward()
+        inf = model.info()
+        e_ms += inf["e_kernel_ms"]
+        h_ms += inf["h_kernel_ms"]
+        e_n += inf["e_launches"]
+        h_n += inf["h_launches"]
+        dev_ms += inf["forward_ms"]
+    wall = time.perf_counter() - t0
+    info = model.info()
+    model.close()
+    nt = info["nt"]
+    cells = info["cells"]
+    ms_per_step = wall / args.steps * 1e3
+    value = cells * nt * args.steps / wall / 1e9
+    e_avg_s = e_ms / e_n / 1e3
+    h_avg_s = h_ms / h_n / 1e3
+    achieved = info["e_bytes"] / e_avg_s / 1e9
+    log(f"[bench] nt={nt} wall/forward={ms_per_step:.1f} ms device loop/forward="
+        f"{dev_ms / args.steps:.1f} ms e_step avg={e_avg_s * 1e6:.2f} us "
+        f"h_step avg={h_avg_s * 1e6:.2f} us tile_kz={info['tile_kz']}")
+    out = {
+        "metric": "FDTD cell-updates/s (Gcell*step/s) + % HBM peak",
+        "value": value, "unit": "Gcell*step/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (fields), f64 (DFT)",
+        "data": "synthetic",
+        "config": {"workload": w.name, "padded_cells": cells, "time_steps": nt,
+                   "rd": w.rd, "sources": len(w.sources), "receivers": len(w.receivers),
+                   "channels": 6, "freqs": [float(f) for f in w.freqs],
+                   "step": "one full forward modelling (nt time steps)"},
+        "roofline": {"bound": "hbm", "kernel": "e_step (curl H + CPML + J + E update + H DTFT)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": E_STEP_TRAFFIC_BYTES,
+                     "bytes_per_launch": info["e_bytes"], "avg_launch_us": e_avg_s * 1e6},
+        "h_step": {"bytes_per_launch": info["h_bytes"], "avg_launch_us": h_avg_s * 1e6,
+                   "achieved_GBs": info["h_bytes"] / h_avg_s / 1e9},
+        "device_loop_ms_per_step": dev_ms / args.steps,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host cores")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

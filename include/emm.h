@@ -1,0 +1,145 @@
+/*
+ * emm.h -- C ABI of the MI355X fictitious-wave-domain CSEM FDTD library.
+ *
+ * What it computes (Yang, "libEMM", arXiv:2304.00233):
+ *   Given a resistivity model on a rectilinear (possibly non-uniform) mesh,
+ *   electric dipole sources, receivers and frequencies, it returns the complex
+ *   frequency-domain Green's functions G^EE and G^HE of the diffusive Maxwell
+ *   equations (Section 2.1, eq. 1) at the receivers.  It does so in Mittet's
+ *   fictitious wave domain (Section 2.2, eqs. mittet/correspondence): a
+ *   leap-frog staggered-grid (Yee) FDTD of the lossless wave equations with
+ *   eps = sigma/(2 omega0), high-order finite differences on the non-uniform
+ *   grid (Section 3.1, eqs. HFD1/HFD2), CPML absorbing layers (Section 3.4),
+ *   time step dt = cfl/eta (Section 3.2), and an on-the-fly DTFT of the
+ *   receiver samples (Section 3.5) normalised by the source spectrum
+ *   (Section 2.2, eq. greenfunction).
+ *
+ * Conventions shared by every call:
+ *   - every function returns emm_status: EMM_OK = 0, errors are negative; no
+ *     C++ exception crosses the ABI;
+ *   - all pointers are host pointers; inputs are borrowed for the duration of
+ *     the call and copied, never written; outputs are caller-allocated;
+ *   - 3D arrays are [n3][n2][n1] with x (index 1) fastest (Section 3.8);
+ *   - the time-domain hot loop runs entirely on the GPU, with no host
+ *     involvement between steps; the device is the current HIP device at
+ *     emm_create time;
+ *   - one emm_model per host thread at a time (not thread-safe).
+ */
+#ifndef EMM_H
+#define EMM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct emm_model emm_model;   /* opaque; owned by the caller between create and destroy */
+
+typedef enum {
+    EMM_OK            =  0,
+    EMM_ERR_ARG       = -1,  /* NULL pointer, count out of range, bad option, bad channel mask */
+    EMM_ERR_GRID      = -2,  /* n_d < 2*rd+1 or coordinates not finite / not strictly increasing */
+    EMM_ERR_MODEL     = -3,  /* a resistivity <= 0 or not finite */
+    EMM_ERR_GEOMETRY  = -4,  /* a source/receiver 2*rd stencil leaves the unpadded interior */
+    EMM_ERR_FREQ      = -5,  /* a frequency <= 0 or not finite, or nfreq < 1 */
+    EMM_ERR_CFL       = -6,  /* dt_override > 1/eta without allow_unstable */
+    EMM_ERR_NONFINITE = -7,  /* a DTFT accumulator ended non-finite (unstable run) */
+    EMM_ERR_OOM       = -8,  /* device memory request larger than what is free */
+    EMM_ERR_DEVICE    = -9   /* a HIP call failed; emm_last_error() has the HIP message */
+} emm_status;
+
+/* The model mesh (Section 5, "Physical domain, grid dimensions and
+ * coordinates" and "Resistivity files").  Node coordinates x_d[0..n_d-1] in
+ * metres, strictly increasing, any spacing (the paper allows a non-uniform
+ * z axis; all three axes are accepted here).  rho11/rho22/rho33 are the
+ * homogenized resistivities (ohm-m) at the Ex/Ey/Ez positions, i.e. shifted
+ * by half a cell along x/y/z: rho11[k][j][i] sits at (x_{i+1/2}, y_j, z_k). */
+typedef struct {
+    int n1, n2, n3;
+    const double *x1, *x2, *x3;
+    const float *rho11, *rho22, *rho33;
+} emm_grid;
+
+/* Options; emm_default_options() fills the defaults given in brackets. */
+typedef struct {
+    int    rd;             /* half stencil length r, 1..4: order 2r in space [2] (Section 5, rd) */
+    int    nb;             /* CPML layers per side [10] (Section 3.4) */
+    int    ne;             /* buffer layers between CPML and interior [rd+5 when < 0] */
+    double f0;             /* omega0 = 2 pi f0 of the wave-domain transform, Hz [1.0] */
+    double cfl;            /* dt = cfl/eta [0.99] (Section 3.2) */
+    double dt_override;    /* > 0: use this dt; above 1/eta it is an EMM_ERR_CFL unless allow_unstable [0] */
+    int    nt;             /* time steps; 0 = automatic (wavelet length + DFT kernel decay) [0] */
+    int    dft_mode;       /* 0 = FP64 accumulators, 1 = FP32 with Kahan compensation [0] */
+    double cpml_R;         /* theoretical reflection coefficient [1e-5] */
+    double cpml_npow;      /* profile power N [2] */
+    double cpml_alpha_max; /* frequency-shift maximum; 0 = pi * f_peak [0] */
+    double wavelet_fpeak;  /* source wavelet peak frequency; 0 = 2 sqrt(f_max f0) [0] */
+    int    allow_unstable; /* test hook: accept dt_override above the CFL limit [0] */
+    int    profile;        /* 1 = time every stencil launch with HIP events (emm_query) [0] */
+    int    tile_kz;        /* z planes per thread block; 0 = chosen from the grid [0] */
+} emm_options;
+
+/* A point electric dipole (Section 5, "Survey acquisitions"): position in
+ * metres, component 0/1/2 = Jx/Jy/Jz, moment in A.m (G is per unit moment). */
+typedef struct { double x, y, z; int comp; double moment; } emm_source;
+
+/* A receiver position in metres; every receiver is live for every source. */
+typedef struct { double x, y, z; } emm_receiver;
+
+/* Model and last-run facts. */
+typedef struct {
+    double dt;               /* time step, s */
+    int    nt;               /* steps of the last forward (or the fixed option; 0 before a forward if automatic) */
+    int    n1pad, n2pad, n3pad;
+    long long cells;         /* n1pad * n2pad * n3pad */
+    double bytes_per_step;   /* algorithmic HBM bytes of one e-step + h-step, one source */
+    double e_bytes, h_bytes; /* split of bytes_per_step over the two stencil kernels */
+    /* filled when options.profile = 1: totals over the last forward */
+    double e_kernel_ms, h_kernel_ms;   /* summed kernel durations (HIP events) */
+    long long e_launches, h_launches;
+    double forward_ms;       /* device time of the whole time loop (HIP events) */
+    int    tile_kz;          /* z planes per block actually used */
+} emm_info;
+
+/* Fill *o with the defaults above. */
+emm_status emm_default_options(emm_options *o);
+
+/* Validate the mesh and model, build the padded grid (Section 3.4: nb + ne
+ * layers per side, coordinates extended with the end interval, resistivity
+ * replicated), the FD coefficient tables by solving the transposed
+ * Vandermonde system (Section 3.1, Bjorck-Pereyra), dt (Section 3.2) and
+ * dt/eps per cell, then allocate device memory and upload.  On success *out
+ * owns device memory until emm_destroy.  Errors: ARG, GRID, MODEL, CFL, OOM,
+ * DEVICE; on error *out is NULL. */
+emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out);
+
+/* Copy model facts into *info. Errors: ARG. */
+emm_status emm_query(const emm_model *m, emm_info *info);
+
+/* Run the forward modelling for nsrc independent sources (batched in one
+ * launch per half step) and write
+ *   green[((s*nrec + r)*nchan + c)*nfreq + f] = (re, im)   (2 doubles)
+ * for the channels c enumerated in bit order of chan_mask (bit 0..5 =
+ * Ex, Ey, Ez, Hx, Hy, Hz; the order of the paper's output listing,
+ * Section 5): G^EE in V/(A m^2) for E channels, G^HE in 1/m^2 for H
+ * channels.  green must hold 2*nsrc*nrec*popcount(chan_mask)*nfreq doubles.
+ * hip_stream: a hipStream_t to run on, or NULL for the library's own stream.
+ * Errors: ARG, GEOMETRY, FREQ, NONFINITE, OOM, DEVICE. */
+emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc,
+                       const emm_receiver *rec, int nrec, unsigned chan_mask,
+                       const double *freq_hz, int nfreq, double *green,
+                       void *hip_stream);
+
+/* Free device and host memory. NULL-safe. */
+void emm_destroy(emm_model *m);
+
+/* Static name of a status code. */
+const char *emm_status_str(emm_status s);
+
+/* Detail of the last failure on this thread (validation message or HIP error
+ * string); empty if none.  m may be NULL. */
+const char *emm_last_error(const emm_model *m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMM_H */

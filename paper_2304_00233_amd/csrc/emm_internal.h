@@ -1,0 +1,58 @@
+// Internal types shared by the host runtime and the HIP kernels of libemm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace emm {
+
+constexpr int kTileX = 64;     // one wavefront row along x (wave64)
+constexpr int kMaxR = 4;       // 8th order in space at most
+
+// Everything one half-step kernel needs; passed by value.
+struct StepParams {
+    // padded grid and device layout: [n3][n2][pitch], x fastest
+    int n1, n2, n3, pitch;
+    long long plane;            // pitch * n2
+    long long fstride;          // one source's field array: plane * n3
+    int nb;
+    // launch decomposition
+    int xt, yt, zc, kz;         // x tiles, y tiles, z chunks, planes per chunk
+    int nsrc;
+    int nstencil;               // xt * yt * zc * nsrc
+    int nrecblk;                // receiver blocks placed first (multiple of 8)
+    // fields (source 0; source s at + s * fstride)
+    float *E1, *E2, *E3, *H1, *H2, *H3;
+    const float *ce1, *ce2, *ce3;   // dt/eps at Ex/Ey/Ez positions
+    float ch;                        // dt/mu0
+    // FD tables [n_d][2R]: cm = D- at integer nodes, cp = D+ at half nodes
+    const float *cmx, *cmy, *cmz, *cpx, *cpy, *cpz;
+    // CPML coefficients per axis: integer nodes (E step) and half nodes (H step)
+    const float *axi, *bxi, *ayi, *byi, *azi, *bzi;
+    const float *axh, *bxh, *ayh, *byh, *azh, *bzh;
+    // CPML memory variables of this half step, two per axis, per source:
+    //   x: [n3][n2][2nb], y: [n3][2nb][pitch], z: [2nb][n2][pitch]
+    float *psx0, *psx1, *psy0, *psy1, *psz0, *psz1;
+    long long psxs, psys, pszs;      // per-source strides
+    // sources (E step only): per source {comp, bx, by, bz}, (2R)^3 q values
+    const int *src_info;
+    const float *src_q;
+    const float *wavelet;            // s_n
+    // receiver DFT items handled by this kernel
+    int nitems;
+    const int *item_info;            // per item {src, field 0..2, bx, by, bz, slot}
+    const float *item_w;             // per item wx[2R], wy[2R], wz[2R]
+    const double2 *phase;            // [nt][nf] exp(i w' t) of this kernel's stamp
+    int nf;
+    double2 *acc;                    // [slots][nf]           (dft_mode 0)
+    float4 *acck;                    // [slots][nf] re,cre,im,cim (dft_mode 1)
+    int dft_mode;
+};
+
+void launch_e_step(int r, const StepParams &p, int n, hipStream_t s);
+void launch_h_step(int r, const StepParams &p, int n, hipStream_t s);
+int block_threads();
+
+}  // namespace emm

@@ -1,0 +1,303 @@
+// HIP kernels of the fictitious-wave-domain FDTD hot path, written for
+// CDNA4 (gfx950).
+//
+// One kernel template serves both half steps of the leap-frog scheme
+// (Section 3.1):
+//   E step:  E += (dt/eps) (curl H - J)   curl with D- (eq. HFD2), J = dipole
+//   H step:  H -= (dt/mu0)  curl E        curl with D+ (eq. HFD1)
+// fused with the CPML memory-variable recursion psi = b psi + a d,
+// d <- d + psi inside the absorbing slabs (Section 3.4), the electric dipole
+// injection (E step only) and, in extra waves of the same launch, the
+// receiver interpolation plus the on-the-fly DTFT of Section 3.5 for the
+// fields the kernel only reads (H channels in the E step, E channels in the
+// H step).  No curl arrays are written (the paper's curl and update kernels
+// are one pass here).
+//
+// Work decomposition: a 256-thread block covers a 64 (x) by 4 (y) tile of
+// columns and marches a chunk of z planes.  Each wavefront owns one 64-wide
+// row along x (coalesced 256-byte accesses).  Per plane, the x/y stencil
+// operands are staged in LDS with their halos; the two z-differentiated
+// components live in a 2r-deep register queue per column, so every plane of
+// them is loaded once.  Tiles are mapped to the eight XCDs in contiguous
+// ranges so that neighbouring tiles share an L2.
+#include "emm_internal.h"
+
+namespace emm {
+
+constexpr int TY = 4;
+constexpr int NT = kTileX * TY;
+
+int block_threads() { return NT; }
+
+// Hardware dispatches workgroup w to XCD w % 8; give every XCD one
+// contiguous range of logical tiles.
+__device__ __forceinline__ int xcd_tile(int w, int total) {
+    const int q = total >> 3, rem = total & 7;
+    const int x = w & 7, local = w >> 3;
+    return x * q + min(x, rem) + local;
+}
+
+// Receiver sample + DTFT: one wavefront per (source, receiver, channel)
+// item.  u = sum over the (2r)^3 tensor-product stencil of w * F, reduced in
+// FP64; then acc[f] += u * exp(i w'_f t_n) for every frequency.
+template <int R>
+__device__ void rec_dft(const StepParams &p, int blk, const float *F0,
+                        const float *F1, const float *F2, int n) {
+    constexpr int L = 2 * R;
+    const int lane = threadIdx.x & 63;
+    const int item = blk * (NT / 64) + (threadIdx.x >> 6);
+    if (item >= p.nitems) return;
+    const int *inf = p.item_info + 6 * item;
+    const int s = inf[0], f = inf[1], bx = inf[2], by = inf[3], bz = inf[4], slot = inf[5];
+    const float *w = p.item_w + 3 * L * item;
+    const float *F = (f == 0 ? F0 : (f == 1 ? F1 : F2)) + (long long)s * p.fstride;
+    double u = 0.0;
+    for (int q = lane; q < L * L * L; q += 64) {
+        const int a = q % L, b = (q / L) % L, c = q / (L * L);
+        const float wt = w[a] * w[L + b] * w[2 * L + c];
+        u += (double)wt * (double)F[(long long)(bz + c) * p.plane + (long long)(by + b) * p.pitch + bx + a];
+    }
+    for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
+    if (lane < p.nf) {
+        const double2 ph = p.phase[(long long)n * p.nf + lane];
+        const long long k = (long long)slot * p.nf + lane;
+        if (p.dft_mode == 0) {
+            double2 a = p.acc[k];
+            a.x += u * ph.x;
+            a.y += u * ph.y;
+            p.acc[k] = a;
+        } else {
+            // FP32 Kahan-compensated sum: (re, c_re, im, c_im)
+            float4 a = p.acck[k];
+            const float uf = (float)u;
+            const float xr = uf * (float)ph.x, xi = uf * (float)ph.y;
+            float y = xr - a.y, t = a.x + y;
+            a.y = (t - a.x) - y;
+            a.x = t;
+            y = xi - a.w;
+            t = a.z + y;
+            a.w = (t - a.z) - y;
+            a.z = t;
+            p.acck[k] = a;
+        }
+    }
+}
+
+// HS = false: E step (reads H, updates E, D- tables, integer-node CPML,
+//             injects J, records H channels);
+// HS = true:  H step (reads E, updates H, D+ tables, half-node CPML,
+//             records E channels).
+template <int R, bool HS>
+__global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n) {
+    constexpr int L = 2 * R;
+    constexpr int HL = HS ? R - 1 : R;        // halo below the own index
+    constexpr int W = kTileX + L - 1;         // LDS row length incl. halo
+    constexpr int HR = TY + L - 1;            // LDS rows incl. halo
+    __shared__ float sA3[HR][W];              // x and y taps
+    __shared__ float sA2[TY][W];              // x taps
+    __shared__ float sA1[HR][kTileX];         // y taps
+
+    const float *A1 = HS ? p.E1 : p.H1;
+    const float *A2 = HS ? p.E2 : p.H2;
+    const float *A3 = HS ? p.E3 : p.H3;
+
+    const int blk = blockIdx.x;
+    if (blk < p.nrecblk) {
+        rec_dft<R>(p, blk, A1, A2, A3, n);
+        return;
+    }
+    int t = xcd_tile(blk - p.nrecblk, p.nstencil);
+    const int bxt = t % p.xt;
+    t /= p.xt;
+    const int byt = t % p.yt;
+    t /= p.yt;
+    const int bzt = t % p.zc;
+    const int s = t / p.zc;
+
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int i0 = bxt * kTileX, j0 = R + byt * TY;
+    const int i = i0 + tx, j = j0 + ty;
+    const int k0 = R + bzt * p.kz;
+    const int k1 = min(k0 + p.kz, p.n3 - R);
+    const bool valid = i >= R && i <= p.n1 - 1 - R && j <= p.n2 - 1 - R;
+    const int jc = min(j, p.n2 - 1);
+    const long long fo = (long long)s * p.fstride;
+    A1 += fo;
+    A2 += fo;
+    A3 += fo;
+    float *U1 = (HS ? p.H1 : p.E1) + fo;
+    float *U2 = (HS ? p.H2 : p.E2) + fo;
+    float *U3 = (HS ? p.H3 : p.E3) + fo;
+
+    const float *tx_ = HS ? p.cpx : p.cmx;
+    const float *ty_ = HS ? p.cpy : p.cmy;
+    const float *tz_ = HS ? p.cpz : p.cmz;
+    const int ic = valid ? i : R;
+    float cx[L], cy[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) {
+        cx[m] = tx_[ic * L + m];
+        cy[m] = ty_[jc * L + m];
+    }
+
+    // CPML slabs: index < nb or > n - 1 - nb on the derivative's own axis
+    const int nb = p.nb, nb2 = 2 * p.nb;
+    const bool xs = valid && (i < nb || i > p.n1 - 1 - nb);
+    const bool ys = valid && (j < nb || j > p.n2 - 1 - nb);
+    float ax = 0.f, bx = 0.f, ay = 0.f, by = 0.f;
+    int ix = 0, jy = 0;
+    if (xs) {
+        ax = (HS ? p.axh : p.axi)[i];
+        bx = (HS ? p.bxh : p.bxi)[i];
+        ix = i < nb ? i : i - (p.n1 - nb2);
+    }
+    if (ys) {
+        ay = (HS ? p.ayh : p.ayi)[j];
+        by = (HS ? p.byh : p.byi)[j];
+        jy = j < nb ? j : j - (p.n2 - nb2);
+    }
+    const float *az_ = HS ? p.azh : p.azi;
+    const float *bz_ = HS ? p.bzh : p.bzi;
+    float *px0 = p.psx0 + s * p.psxs, *px1 = p.psx1 + s * p.psxs;
+    float *py0 = p.psy0 + s * p.psys, *py1 = p.psy1 + s * p.psys;
+    float *pz0 = p.psz0 + s * p.pszs, *pz1 = p.psz1 + s * p.pszs;
+
+    // dipole source of this block's source (E step only)
+    int scomp = -1, sbx = 0, sby = 0, sbz = 0;
+    float sn = 0.f;
+    const float *sq = nullptr;
+    if (!HS) {
+        scomp = p.src_info[4 * s];
+        sbx = p.src_info[4 * s + 1];
+        sby = p.src_info[4 * s + 2];
+        sbz = p.src_info[4 * s + 3];
+        sn = p.wavelet[n];
+        sq = p.src_q + (long long)s * L * L * L;
+    }
+
+    // z queues of the two z-differentiated components: planes k-HL .. k-HL+L-1
+    const long long col = (long long)jc * p.pitch + i;
+    float q1[L], q2[L];
+#pragma unroll
+    for (int m = 0; m < L - 1; ++m) {
+        q1[m] = A1[(long long)(k0 - HL + m) * p.plane + col];
+        q2[m] = A2[(long long)(k0 - HL + m) * p.plane + col];
+    }
+
+    for (int k = k0; k < k1; ++k) {
+        const long long pk = (long long)k * p.plane;
+        q1[L - 1] = A1[(long long)(k - HL + L - 1) * p.plane + col];
+        q2[L - 1] = A2[(long long)(k - HL + L - 1) * p.plane + col];
+
+        // stage plane k: A3 with x and y halos, A2 with x halo, A1 with y halo
+        for (int e = tid; e < HR * W; e += NT) {
+            const int ly = e / W, lx = e - ly * W;
+            const int gj = j0 - HL + ly, gi = i0 - HL + lx;
+            float v = 0.f;
+            if (gj >= 0 && gj < p.n2 && gi >= 0 && gi < p.pitch)
+                v = A3[pk + (long long)gj * p.pitch + gi];
+            sA3[ly][lx] = v;
+        }
+        sA2[ty][tx + HL] = q2[HL];
+        if (tid < TY * (L - 1)) {
+            const int hy = tid / (L - 1), hx = tid % (L - 1);
+            const int lx = hx < HL ? hx : kTileX + hx;
+            const int gi = i0 - HL + lx, gj = min(j0 + hy, p.n2 - 1);
+            float v = 0.f;
+            if (gi >= 0 && gi < p.pitch) v = A2[pk + (long long)gj * p.pitch + gi];
+            sA2[hy][lx] = v;
+        }
+        sA1[ty + HL][tx] = q1[HL];
+        for (int e = tid; e < (L - 1) * kTileX; e += NT) {
+            const int hy = e / kTileX, hx = e - hy * kTileX;
+            const int ly = hy < HL ? hy : TY + hy;
+            const int gj = j0 - HL + ly;
+            float v = 0.f;
+            if (gj >= 0 && gj < p.n2) v = A1[pk + (long long)gj * p.pitch + i0 + hx];
+            sA1[ly][hx] = v;
+        }
+        __syncthreads();
+
+        if (valid) {
+            const float *cz = tz_ + k * L;
+            float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
+#pragma unroll
+            for (int m = 0; m < L; ++m) {
+                d2a3 += cy[m] * sA3[ty + m][tx + HL];
+                d2a1 += cy[m] * sA1[ty + m][tx];
+                d1a3 += cx[m] * sA3[ty + HL][tx + m];
+                d1a2 += cx[m] * sA2[ty][tx + m];
+                d3a2 += cz[m] * q2[m];
+                d3a1 += cz[m] * q1[m];
+            }
+            if (xs) {
+                const long long id = ((long long)k * p.n2 + j) * nb2 + ix;
+                float v = bx * px0[id] + ax * d1a3;
+                px0[id] = v;
+                d1a3 += v;
+                v = bx * px1[id] + ax * d1a2;
+                px1[id] = v;
+                d1a2 += v;
+            }
+            if (ys) {
+                const long long id = ((long long)k * nb2 + jy) * p.pitch + i;
+                float v = by * py0[id] + ay * d2a3;
+                py0[id] = v;
+                d2a3 += v;
+                v = by * py1[id] + ay * d2a1;
+                py1[id] = v;
+                d2a1 += v;
+            }
+            if (k < nb || k > p.n3 - 1 - nb) {
+                const int kz = k < nb ? k : k - (p.n3 - nb2);
+                const float az = az_[k], bz = bz_[k];
+                const long long id = ((long long)kz * p.n2 + j) * p.pitch + i;
+                float v = bz * pz0[id] + az * d3a2;
+                pz0[id] = v;
+                d3a2 += v;
+                v = bz * pz1[id] + az * d3a1;
+                pz1[id] = v;
+                d3a1 += v;
+            }
+            float c1 = d2a3 - d3a2, c2 = d3a1 - d1a3, c3 = d1a2 - d2a1;
+            const long long g = pk + (long long)j * p.pitch + i;
+            if (HS) {
+                U1[g] -= p.ch * c1;
+                U2[g] -= p.ch * c2;
+                U3[g] -= p.ch * c3;
+            } else {
+                if (k >= sbz && k < sbz + L && j >= sby && j < sby + L && i >= sbx && i < sbx + L) {
+                    const float jv = sn * sq[((k - sbz) * L + (j - sby)) * L + (i - sbx)];
+                    if (scomp == 0) c1 -= jv;
+                    else if (scomp == 1) c2 -= jv;
+                    else c3 -= jv;
+                }
+                U1[g] += p.ce1[g] * c1;
+                U2[g] += p.ce2[g] * c2;
+                U3[g] += p.ce3[g] * c3;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < L - 1; ++m) {
+            q1[m] = q1[m + 1];
+            q2[m] = q2[m + 1];
+        }
+    }
+}
+
+template <bool HS>
+static void launch(int r, const StepParams &p, int n, hipStream_t s) {
+    const dim3 grid(p.nrecblk + p.nstencil), block(NT);
+    switch (r) {
+    case 1: hipLaunchKernelGGL((step_kernel<1, HS>), grid, block, 0, s, p, n); break;
+    case 2: hipLaunchKernelGGL((step_kernel<2, HS>), grid, block, 0, s, p, n); break;
+    case 3: hipLaunchKernelGGL((step_kernel<3, HS>), grid, block, 0, s, p, n); break;
+    default: hipLaunchKernelGGL((step_kernel<4, HS>), grid, block, 0, s, p, n); break;
+    }
+}
+
+void launch_e_step(int r, const StepParams &p, int n, hipStream_t s) { launch<false>(r, p, n, s); }
+void launch_h_step(int r, const StepParams &p, int n, hipStream_t s) { launch<true>(r, p, n, s); }
+
+}  // namespace emm

@@ -1,0 +1,128 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/emm.h declares, the ctypes structures match the C layout, default
+options, status strings, and every validation error that emm_create
+reports before touching the device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "emm.h")
+
+
+@pytest.fixture(scope="module")
+def emm():
+    from paper_2304_00233_amd import emm as E
+    return E
+
+
+def test_exports_every_declared_function(emm):
+    names = re.findall(r"^\s*(?:emm_status|void|const char\s*\*)\s*(emm_\w+)\s*\(",
+                       open(HEADER).read(), re.M)
+    assert set(names) == set(emm.EXPORTED)
+    lib = C.CDLL(emm.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", emm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, re.M), n
+
+
+def test_struct_layout_matches_header(emm, tmp_path):
+    src = tmp_path / "layout.c"
+    structs = ["emm_grid", "emm_options", "emm_source", "emm_receiver", "emm_info"]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "emm.h"', "int main(void){"]
+    for s in structs:
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+        for f, _ in getattr(emm, s)._fields_:
+            lines.append(f'printf("{s}.{f} %zu\\n", offsetof({s}, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True,
+                                                        text=True).stdout.split("\n") if l)
+    for s in structs:
+        cls = getattr(emm, s)
+        assert int(got[s]) == C.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert int(got[f"{s}.{f}"]) == getattr(cls, f).offset, (s, f)
+
+
+def test_default_options(emm):
+    o = emm.emm_default_options()
+    assert (o.rd, o.nb, o.ne, o.f0, o.cfl, o.nt, o.dft_mode) == (2, 10, -1, 1.0, 0.99, 0, 0)
+    assert o.cpml_R == 1e-5 and o.cpml_npow == 2.0 and o.profile == 0
+
+
+def test_status_strings(emm):
+    for code, name in emm.STATUS.items():
+        assert emm.emm_status_str(code) == name
+
+
+def _grid(n=(12, 11, 10), rho=1.0):
+    xs = [np.arange(k, dtype=np.float64) * 100.0 for k in n]
+    r = np.full((n[2], n[1], n[0]), rho, np.float32)
+    return xs, [r, r.copy(), r.copy()]
+
+
+def _create_status(emm, xs, rs, **opt):
+    o = emm.emm_default_options()
+    for k, v in opt.items():
+        setattr(o, k, v)
+    try:
+        h = emm.emm_create(*xs, *rs, o)
+    except emm.EmmError as e:
+        return e.status, str(e)
+    emm.emm_destroy(h)
+    return 0, ""
+
+
+def test_create_validation_errors(emm):
+    xs, rs = _grid()
+    assert _create_status(emm, xs, rs, rd=0)[0] == -1
+    assert _create_status(emm, xs, rs, rd=5)[0] == -1
+    assert _create_status(emm, xs, rs, nb=-1)[0] == -1
+    assert _create_status(emm, xs, rs, f0=0.0)[0] == -1
+    assert _create_status(emm, xs, rs, cpml_R=2.0)[0] == -1
+    # too few nodes for the stencil
+    xs2, rs2 = _grid((12, 11, 4))
+    assert _create_status(emm, xs2, rs2, rd=2)[0] == -2
+    # non-monotone and non-finite coordinates
+    bad = [x.copy() for x in xs]
+    bad[1][5] = bad[1][4]
+    assert _create_status(emm, bad, rs)[0] == -2
+    bad = [x.copy() for x in xs]
+    bad[2][3] = np.nan
+    assert _create_status(emm, bad, rs)[0] == -2
+    # resistivity <= 0 or not finite
+    for v in (0.0, -1.0, np.nan, np.inf):
+        r2 = [a.copy() for a in rs]
+        r2[2][1, 2, 3] = v
+        assert _create_status(emm, xs, r2)[0] == -3, v
+    # dt above the CFL limit
+    st, msg = _create_status(emm, xs, rs, dt_override=1.0)
+    assert st == -6 and "stability" in msg
+
+
+def test_null_pointers(emm):
+    lib = emm._lib
+    h = C.c_void_p()
+    assert lib.emm_create(None, None, C.byref(h)) == -1
+    assert lib.emm_default_options(None) == -1
+    assert lib.emm_query(None, None) == -1
+    assert lib.emm_forward(None, None, 0, None, 0, 0, None, 0, None, None) == -1
+    lib.emm_destroy(None)                           # NULL-safe
+
+
+def test_valid_create_without_gpu_reports_device(emm):
+    if os.path.exists("/dev/kfd"):
+        pytest.skip("a GPU is present")
+    xs, rs = _grid()
+    st, msg = _create_status(emm, xs, rs)
+    assert st == -9 and msg

@@ -1,0 +1,150 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every case runs the same seeded synthetic inputs through both and applies
+the rule of tests/parity.py: <= 1e-4 relative amplitude and <= 0.1 degree
+phase for every result above the floor.  Cases span several 64 x 4 tiles
+and z chunks with ragged tails, r = 1..4, non-uniform axes, CPML on and
+off, all three source components in one batched launch, all six receiver
+channels, both accumulator modes; plus run-to-run and tile-shape bitwise
+determinism, the full-size marine layered workload against a stored oracle
+result, and the error paths that need a device.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import analytic as A
+from oracle import forward as F
+from tests.parity import compare
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "marine_layered_oracle.json")
+
+
+@pytest.fixture(scope="module")
+def emm():
+    from paper_2304_00233_amd import emm as E
+    return E
+
+
+def _run(emm, w, **opt):
+    print(f"[gpu] {w.name} nsrc={len(w.sources)} nrec={len(w.receivers)} rd={w.rd} "
+          f"nt={w.nt} opts={opt}", flush=True)
+    G, info = emm.forward_workload(w, **opt)
+    return G, info
+
+
+def _check(emm, w, label, **opt):
+    G_o, info_o = F.forward(w)
+    G_g, info_g = _run(emm, w.with_(nt=info_o["nt"]), **opt)
+    rep = compare(G_g, G_o, w.channels)
+    print(f"[parity] {label}: {rep}", flush=True)
+    assert info_g["dt"] == pytest.approx(info_o["dt"], rel=1e-12)
+    assert (info_g["n1pad"], info_g["n2pad"], info_g["n3pad"]) == tuple(info_o["n_pad"])
+    assert info_g["nt"] == info_o["nt"]
+    assert rep["ok"], rep
+    return G_g, G_o, rep
+
+
+def _plain_with_offaxis():
+    w = configs.plain_forward()
+    xs = np.array([-1800.0, -1200.0, -600.0, 600.0, 1200.0, 1800.0])
+    off = np.stack([xs, np.full_like(xs, 450.0), np.full_like(xs, -350.0)], axis=1)
+    return w.with_(receivers=np.concatenate([w.receivers, off]))
+
+
+def test_plain_forward_48cube(emm):
+    w = _plain_with_offaxis()
+    G_g, _, _ = _check(emm, w, "plain_forward_48cube")
+    # the GPU result is also close to the analytic whole-space dipole
+    rec = w.receivers[21:]
+    E, _ = A.dipole_fields([0, 0, 0], [1, 0, 0], rec, 1.0, 1.0)
+    assert np.max(np.abs(G_g[0, 21:, 0, 0] / E[:, 0] - 1)) < 0.02
+
+
+SMALL = [
+    dict(seed=0),
+    dict(seed=1, rd=1, shape=(30, 27, 25), nu_axes=(True, True, True)),
+    dict(seed=2, rd=3, shape=(33, 31, 29), nu_axes=(False, True, True)),
+    dict(seed=3, rd=4, shape=(41, 35, 33), nb=8),
+    dict(seed=4, shape=(70, 13, 11), nb=4, nrec=9),                  # two x tiles, ragged
+    dict(seed=5, shape=(23, 22, 21), nb=0, ne=3, nt=400),            # no CPML
+    dict(seed=6, nsrc=3, src_comp=(0, 1, 2), shape=(31, 30, 26)),    # batched sources
+    dict(seed=7, rd=2, shape=(26, 24, 40), freqs=(0.3, 0.9, 2.7, 5.0)),
+]
+
+
+@pytest.mark.parametrize("kw", SMALL, ids=[f"s{c['seed']}" for c in SMALL])
+def test_small_cases(emm, kw):
+    w = configs.small_case(**kw)
+    _check(emm, w, w.name)
+
+
+def test_kahan_fp32_accumulators(emm):
+    w = configs.small_case(seed=8, shape=(29, 27, 25), nt=300)
+    _, _, rep = _check(emm, w, "kahan", dft_mode=1)
+
+
+def test_bitwise_determinism_runs_and_tiles(emm):
+    w = configs.small_case(seed=9, shape=(40, 30, 37), nt=200)
+    G1, _ = _run(emm, w)
+    G2, _ = _run(emm, w)
+    G3, i3 = _run(emm, w, tile_kz=3)
+    assert i3["tile_kz"] == 3
+    assert np.array_equal(G1, G2)
+    assert np.array_equal(G1, G3)
+
+
+def test_batched_equals_single_sources(emm):
+    w = configs.small_case(seed=10, nsrc=4, shape=(28, 26, 24), nt=200)
+    Gb, _ = _run(emm, w)
+    for s in range(4):
+        Gs, _ = _run(emm, w.with_(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1]))
+        assert np.array_equal(Gb[s:s + 1], Gs)
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="marine oracle result not generated")
+def test_marine_layered_full_size_vs_stored_oracle(emm):
+    g = json.load(open(GOLDEN))
+    G_o = (np.array(g["re"]) + 1j * np.array(g["im"])).reshape(g["shape"])
+    w = configs.marine_layered(nt=g["nt"])
+    G_g, info = _run(emm, w)
+    assert info["dt"] == pytest.approx(g["dt"], rel=1e-12)
+    rep = compare(G_g, G_o, g["channels"])
+    print(f"[parity] marine_layered_128x128x96 full size: {rep}", flush=True)
+    assert rep["ok"], rep
+
+
+def test_error_paths_on_device(emm):
+    w = configs.small_case(seed=11, shape=(21, 20, 19), nt=50)
+    with emm.Model(w) as m:
+        with pytest.raises(emm.EmmError) as e:
+            m.forward(receivers=np.array([[1e6, 0.0, 0.0]]))
+        assert e.value.status == -4
+        with pytest.raises(emm.EmmError) as e:
+            m.forward(freqs=np.array([-1.0]))
+        assert e.value.status == -5
+        with pytest.raises(emm.EmmError) as e:
+            m.forward(chan_mask=0)
+        assert e.value.status == -1
+        G = m.forward()                     # the model is still usable
+        assert np.all(np.isfinite(G))
+    # an unstable time step (forced from the host) ends non-finite, reported as such
+    probe = emm.Model(w)
+    dt = probe.info()["dt"]
+    probe.close()
+    with emm.Model(w.with_(nt=400), dt_override=3.0 * dt / 0.99, allow_unstable=1) as m:
+        with pytest.raises(emm.EmmError) as e:
+            m.forward()
+        assert e.value.status == -7
+
+
+def test_profile_counters(emm):
+    w = configs.small_case(seed=12, shape=(30, 28, 26), nt=120)
+    G, info = _run(emm, w, profile=1)
+    assert info["e_launches"] == 120 and info["h_launches"] == 120
+    assert 0 < info["e_kernel_ms"] < info["forward_ms"]
+    assert 0 < info["h_kernel_ms"] < info["forward_ms"]

@@ -182,7 +182,7 @@ def batched_models(count: int = 8, nt: int = 0) -> list[Workload]:
 # and receivers, all six channels.  Sized so the oracle finishes in seconds.
 # --------------------------------------------------------------------------
 def small_case(seed: int = 0, shape=(37, 29, 23), rd: int = 2, nb: int = 6,
-               ne: int | None = None, nt: int = 240, nu_axes=(False, False, True),
+               ne: int | None = None, nt: int = 600, nu_axes=(False, False, True),
                nsrc: int = 1, nrec: int = 7, freqs=(0.5, 1.5),
                src_comp=None) -> Workload:
     rng = np.random.default_rng(1000 + seed)
