@@ -55,21 +55,47 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--workload", default="marine", choices=["marine", "large", "cube"],
+                    help="marine: the headline 128x128x96 workload; large: the 400x400x200 "
+                         "marine grid (one source); cube: uniform n^3 (--cube-n)")
+    ap.add_argument("--cube-n", type=int, default=400)
+    ap.add_argument("--rd", type=int, default=0, help="override the stencil half length")
+    ap.add_argument("--nt", type=int, default=0, help="override the time-step count")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {a.numel() * 4} bytes")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by "
-              "source with no communication, see DESIGN.md", file=sys.stderr)
+              "source with no communication between GPUs", file=sys.stderr)
         sys.exit(2)
 
     from paper_2304_00233_amd import emm
     from workloads import configs
 
-    w = configs.marine_layered()
-    nt = 0
-    gold = os.path.join(ROOT, "tests", "golden", "marine_layered_oracle.json")
-    if os.path.exists(gold):
-        nt = json.load(open(gold))["nt"]
-    w = w.with_(nt=nt)
+    if args.workload == "marine":
+        w = configs.marine_layered()
+        nt = 0
+        gold = os.path.join(ROOT, "tests", "golden", "marine_layered_oracle.json")
+        if os.path.exists(gold):
+            nt = json.load(open(gold))["nt"]
+        w = w.with_(nt=nt)
+    elif args.workload == "large":
+        w = configs.large_marine(nsrc=1).with_(dft_mode=0)
+    else:
+        w = configs.uniform_cube(args.cube_n)
+    if args.rd:
+        w = w.with_(rd=args.rd, ne=args.rd + 5)
+    if args.nt:
+        w = w.with_(nt=args.nt)
     log(f"[bench] workload {w.name} padded cells {w.padded_cells}")
 
     model = emm.Model(w, profile=1)

@@ -87,15 +87,25 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
 //             injects J, records H channels);
 // HS = true:  H step (reads E, updates H, D+ tables, half-node CPML,
 //             records E channels).
+//
+// Per plane k the loop (i) moves the staged operands of plane k from
+// registers into one of two LDS buffers, (ii) passes one barrier, (iii)
+// issues every global load of plane k+1 (staging, queue edge, updated field,
+// dt/eps), and (iv) computes plane k from LDS and registers while those
+// loads are in flight.  Two LDS buffers make one barrier per plane enough: a
+// buffer is rewritten only after every wave has passed the barrier that
+// follows its last use.
 template <int R, bool HS>
 __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n) {
     constexpr int L = 2 * R;
     constexpr int HL = HS ? R - 1 : R;        // halo below the own index
     constexpr int W = kTileX + L - 1;         // LDS row length incl. halo
     constexpr int HR = TY + L - 1;            // LDS rows incl. halo
-    __shared__ float sA3[HR][W];              // x and y taps
-    __shared__ float sA2[TY][W];              // x taps
-    __shared__ float sA1[HR][kTileX];         // y taps
+    constexpr int N3 = (HR * W + NT - 1) / NT;              // A3 staging loads per thread
+    constexpr int N1 = ((L - 1) * kTileX + NT - 1) / NT;    // A1 halo loads per thread
+    __shared__ float sA3[2][HR][W];           // x and y taps
+    __shared__ float sA2[2][TY][W];           // x taps
+    __shared__ float sA1[2][HR][kTileX];      // y taps
 
     const float *A1 = HS ? p.E1 : p.H1;
     const float *A2 = HS ? p.E2 : p.H2;
@@ -175,58 +185,101 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n) {
         sq = p.src_q + (long long)s * L * L * L;
     }
 
+    // Staging map (identical for every plane): element e of the A3 tile is
+    // row e / W, column e % W of the LDS tile, i.e. global (j0 - HL + row,
+    // i0 - HL + col); out-of-array elements stage zeros.
+    // (LDS index of A3 element u: tid + u * NT; of A1 halo element u: row
+    // ly1(u) * 64 + tx.)
+    int o3[N3];        // plane offset, or -1 (outside the array or the tile)
+#pragma unroll
+    for (int u = 0; u < N3; ++u) {
+        const int e = tid + u * NT;
+        const int ly = e / W, lx = e - ly * W;
+        const int gj = j0 - HL + ly, gi = i0 - HL + lx;
+        o3[u] = (e < HR * W && gj >= 0 && gj < p.n2 && gi >= 0 && gi < p.pitch) ? gj * p.pitch + gi : -1;
+    }
+    auto ly1 = [&](int u) {
+        const int hy = (tid + u * NT) >> 6;
+        return hy < HL ? hy : TY + hy;
+    };
+    int o1[N1];
+#pragma unroll
+    for (int u = 0; u < N1; ++u) {
+        const int e = tid + u * NT;
+        const int gj = j0 - HL + ly1(u);
+        o1[u] = (e < (L - 1) * kTileX && gj >= 0 && gj < p.n2) ? gj * p.pitch + i0 + tx : -1;
+    }
+    int o2 = -1, l2 = -1;
+    if (tid < TY * (L - 1)) {
+        const int hy = tid / (L - 1), hx = tid % (L - 1);
+        const int lx = hx < HL ? hx : kTileX + hx;
+        const int gi = i0 - HL + lx, gj = min(j0 + hy, p.n2 - 1);
+        l2 = hy * W + lx;
+        o2 = (gi >= 0 && gi < p.pitch) ? gj * p.pitch + gi : -1;
+    }
+    const int own = jc * p.pitch + i;          // plane offset of this thread's column
+
     // z queues of the two z-differentiated components: planes k-HL .. k-HL+L-1
-    const long long col = (long long)jc * p.pitch + i;
     float q1[L], q2[L];
 #pragma unroll
     for (int m = 0; m < L - 1; ++m) {
-        q1[m] = A1[(long long)(k0 - HL + m) * p.plane + col];
-        q2[m] = A2[(long long)(k0 - HL + m) * p.plane + col];
+        q1[m] = A1[(long long)(k0 - HL + m) * p.plane + own];
+        q2[m] = A2[(long long)(k0 - HL + m) * p.plane + own];
     }
 
-    for (int k = k0; k < k1; ++k) {
+    // staged registers of the next plane
+    float f3[N3], f1[N1], f2 = 0.f, e1n, e2n;
+    float un1 = 0.f, un2 = 0.f, un3 = 0.f, cn1 = 0.f, cn2 = 0.f, cn3 = 0.f;
+    auto issue = [&](int k) {
         const long long pk = (long long)k * p.plane;
-        q1[L - 1] = A1[(long long)(k - HL + L - 1) * p.plane + col];
-        q2[L - 1] = A2[(long long)(k - HL + L - 1) * p.plane + col];
+#pragma unroll
+        for (int u = 0; u < N3; ++u) f3[u] = o3[u] >= 0 ? A3[pk + o3[u]] : 0.f;
+#pragma unroll
+        for (int u = 0; u < N1; ++u) f1[u] = o1[u] >= 0 ? A1[pk + o1[u]] : 0.f;
+        if (o2 >= 0) f2 = A2[pk + o2];
+        e1n = A1[(long long)(k - HL + L - 1) * p.plane + own];
+        e2n = A2[(long long)(k - HL + L - 1) * p.plane + own];
+        if (valid) {
+            un1 = U1[pk + own];
+            un2 = U2[pk + own];
+            un3 = U3[pk + own];
+            if (!HS) {
+                cn1 = p.ce1[pk + own];
+                cn2 = p.ce2[pk + own];
+                cn3 = p.ce3[pk + own];
+            }
+        }
+    };
+    issue(k0);
 
-        // stage plane k: A3 with x and y halos, A2 with x halo, A1 with y halo
-        for (int e = tid; e < HR * W; e += NT) {
-            const int ly = e / W, lx = e - ly * W;
-            const int gj = j0 - HL + ly, gi = i0 - HL + lx;
-            float v = 0.f;
-            if (gj >= 0 && gj < p.n2 && gi >= 0 && gi < p.pitch)
-                v = A3[pk + (long long)gj * p.pitch + gi];
-            sA3[ly][lx] = v;
-        }
-        sA2[ty][tx + HL] = q2[HL];
-        if (tid < TY * (L - 1)) {
-            const int hy = tid / (L - 1), hx = tid % (L - 1);
-            const int lx = hx < HL ? hx : kTileX + hx;
-            const int gi = i0 - HL + lx, gj = min(j0 + hy, p.n2 - 1);
-            float v = 0.f;
-            if (gi >= 0 && gi < p.pitch) v = A2[pk + (long long)gj * p.pitch + gi];
-            sA2[hy][lx] = v;
-        }
-        sA1[ty + HL][tx] = q1[HL];
-        for (int e = tid; e < (L - 1) * kTileX; e += NT) {
-            const int hy = e / kTileX, hx = e - hy * kTileX;
-            const int ly = hy < HL ? hy : TY + hy;
-            const int gj = j0 - HL + ly;
-            float v = 0.f;
-            if (gj >= 0 && gj < p.n2) v = A1[pk + (long long)gj * p.pitch + i0 + hx];
-            sA1[ly][hx] = v;
-        }
+    for (int k = k0; k < k1; ++k) {
+        const int b = (k - k0) & 1;
+        q1[L - 1] = e1n;
+        q2[L - 1] = e2n;
+        float *s3 = &sA3[b][0][0];
+#pragma unroll
+        for (int u = 0; u < N3; ++u)
+            if (u < N3 - 1 || tid + u * NT < HR * W) s3[tid + u * NT] = f3[u];
+        float *s1 = &sA1[b][0][0];
+#pragma unroll
+        for (int u = 0; u < N1; ++u)
+            if (u < N1 - 1 || tid + u * NT < (L - 1) * kTileX) s1[ly1(u) * kTileX + tx] = f1[u];
+        if (l2 >= 0) (&sA2[b][0][0])[l2] = o2 >= 0 ? f2 : 0.f;
+        sA2[b][ty][tx + HL] = q2[HL];
+        sA1[b][ty + HL][tx] = q1[HL];
+        const float u1 = un1, u2 = un2, u3 = un3, ce1 = cn1, ce2 = cn2, ce3 = cn3;
         __syncthreads();
+        if (k + 1 < k1) issue(k + 1);
 
         if (valid) {
             const float *cz = tz_ + k * L;
             float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
 #pragma unroll
             for (int m = 0; m < L; ++m) {
-                d2a3 += cy[m] * sA3[ty + m][tx + HL];
-                d2a1 += cy[m] * sA1[ty + m][tx];
-                d1a3 += cx[m] * sA3[ty + HL][tx + m];
-                d1a2 += cx[m] * sA2[ty][tx + m];
+                d2a3 += cy[m] * sA3[b][ty + m][tx + HL];
+                d2a1 += cy[m] * sA1[b][ty + m][tx];
+                d1a3 += cx[m] * sA3[b][ty + HL][tx + m];
+                d1a2 += cx[m] * sA2[b][ty][tx + m];
                 d3a2 += cz[m] * q2[m];
                 d3a1 += cz[m] * q1[m];
             }
@@ -260,11 +313,11 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n) {
                 d3a1 += v;
             }
             float c1 = d2a3 - d3a2, c2 = d3a1 - d1a3, c3 = d1a2 - d2a1;
-            const long long g = pk + (long long)j * p.pitch + i;
+            const long long g = (long long)k * p.plane + own;
             if (HS) {
-                U1[g] -= p.ch * c1;
-                U2[g] -= p.ch * c2;
-                U3[g] -= p.ch * c3;
+                U1[g] = u1 - p.ch * c1;
+                U2[g] = u2 - p.ch * c2;
+                U3[g] = u3 - p.ch * c3;
             } else {
                 if (k >= sbz && k < sbz + L && j >= sby && j < sby + L && i >= sbx && i < sbx + L) {
                     const float jv = sn * sq[((k - sbz) * L + (j - sby)) * L + (i - sbx)];
@@ -272,12 +325,11 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n) {
                     else if (scomp == 1) c2 -= jv;
                     else c3 -= jv;
                 }
-                U1[g] += p.ce1[g] * c1;
-                U2[g] += p.ce2[g] * c2;
-                U3[g] += p.ce3[g] * c3;
+                U1[g] = u1 + ce1 * c1;
+                U2[g] = u2 + ce2 * c2;
+                U3[g] = u3 + ce3 * c3;
             }
         }
-        __syncthreads();
 #pragma unroll
         for (int m = 0; m < L - 1; ++m) {
             q1[m] = q1[m + 1];

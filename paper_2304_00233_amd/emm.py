@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libemm.so")
+# EMM_LIBRARY may point at another build of the same ABI (e.g. an older
+# kernel version for an A/B timing); default: the in-tree build.
+LIB_PATH = os.environ.get("EMM_LIBRARY") or os.path.join(_HERE, "libemm.so")
 
 EMM_OK = 0
 STATUS = {0: "EMM_OK", -1: "EMM_ERR_ARG", -2: "EMM_ERR_GRID", -3: "EMM_ERR_MODEL",

@@ -126,3 +126,24 @@ def test_valid_create_without_gpu_reports_device(emm):
     xs, rs = _grid()
     st, msg = _create_status(emm, xs, rs)
     assert st == -9 and msg
+
+
+@pytest.mark.parametrize("rd", [1, 2, 3, 4])
+def test_host_stability_limit_matches_oracle(emm, rd):
+    """emm_create computes eta = 1/2 v_max sqrt(sum D_d^2) (Section 3.2) from
+    its Bjorck-Pereyra tables before any device call; the oracle computes it
+    from Fornberg tables.  A dt_override a hair above the oracle's 1/eta must
+    be rejected (CFL) and a hair below accepted by validation, on a
+    non-uniform grid."""
+    from oracle import forward as F
+    from workloads import configs
+    w = configs.small_case(seed=20 + rd, shape=(19, 17, 16), rd=rd,
+                           nu_axes=(True, True, True))
+    st = F.make_setup(w, fp=2.0)
+    limit = st.dt / w.cfl
+    xs = [w.x1, w.x2, w.x3]
+    rs = [w.rho11, w.rho22, w.rho33]
+    st_hi, _ = _create_status(emm, xs, rs, rd=rd, nb=w.nb, ne=w.ne, dt_override=limit * (1 + 1e-9))
+    assert st_hi == -6
+    st_lo, _ = _create_status(emm, xs, rs, rd=rd, nb=w.nb, ne=w.ne, dt_override=limit * (1 - 1e-9))
+    assert st_lo != -6          # passes validation (then needs a device)
