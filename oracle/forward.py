@@ -58,6 +58,8 @@ def _load():
         _lib = C.CDLL(LIB_PATH)
         _lib.oracle_run.argtypes = [C.POINTER(_Params)]
         _lib.oracle_run.restype = C.c_int
+        _lib.oracle_gradient.argtypes = [C.POINTER(_Params), C.c_int, _dp, _dp, _dp]
+        _lib.oracle_gradient.restype = C.c_int
         for f in (_lib.oracle_curl_h, _lib.oracle_curl_e):
             f.argtypes = [C.POINTER(_Params)] + [_dp] * 6
             f.restype = None
@@ -86,7 +88,10 @@ class Setup:
     ce: tuple            # dt/eps at E1/E2/E3
 
 
-def make_setup(w, fp: float, dt_override: float = 0.0) -> Setup:
+def make_setup(w, fp: float, dt_override: float = 0.0, frozen: "Setup | None" = None) -> Setup:
+    """frozen: take dt and the CPML tables from this reference set-up (both
+    depend on the largest resistivities; a derivative with respect to the
+    model holds them fixed)."""
     r, nb = w.rd, w.nb
     nbe = w.nb + w.ne
     omega0 = 2.0 * np.pi * w.f0
@@ -99,17 +104,17 @@ def make_setup(w, fp: float, dt_override: float = 0.0) -> Setup:
     for a in range(3):
         v_lo, v_hi = T.slab_velocities(rho, a, nb, omega0)
         cpml.append(T.cpml_axis(axes[a], nb, dt, v_lo, v_hi, alpha_max))
+    if frozen is not None:
+        dt, cpml = frozen.dt, list(frozen.cpml)
     # dt * eps^-1 with eps = 1/(2 omega0 rho)  (Section 2.2: sigma = 2 omega0 eps)
     ce = tuple(np.ascontiguousarray(dt * 2.0 * omega0 * a) for a in rho)
     return Setup(r, nb, nbe, axes, tuple(len(x) for x in axes), rho, fd, dt,
                  omega0, fp, tuple(cpml), ce)
 
 
-def run_source(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
-               threads: int | None = None, moment: float = 1.0):
-    """Time-domain run for one source; returns the receiver DTFT
-    acc[nrec][nchan][nfreq] and the source spectrum S_f."""
-    lib = _load()
+def _build_params(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
+                  threads: int | None = None, moment: float = 1.0):
+    """ctypes parameter block for one source plus the arrays it points to."""
     r = st.r
     L = 2 * r
     n1, n2, n3 = st.n_pad
@@ -161,12 +166,88 @@ def run_source(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
     P.phE_re, P.phE_im, P.phH_re, P.phH_im = (_ptr(a) for a in (phE_re, phE_im, phH_re, phH_im))
     P.acc_re, P.acc_im = _ptr(acc_re), _ptr(acc_im)
     P.nthreads = int(threads or os.cpu_count() or 1)
-    keep = (tabs, cp, q, s, ch_arr, rb, rw, phE_re, phE_im, phH_re, phH_im)  # noqa: F841
+    keep = (tabs, cp, q, s, ch_arr, rb, rw, phE_re, phE_im, phH_re, phH_im, acc_re, acc_im)
+    return P, keep, s
+
+
+def run_source(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
+               threads: int | None = None, moment: float = 1.0):
+    """Time-domain run for one source; returns the receiver DTFT
+    acc[nrec][nchan][nfreq] and the source spectrum S_f."""
+    lib = _load()
+    P, keep, s = _build_params(st, nt, src, comp, rec, chans, freqs, threads, moment)
     rc = lib.oracle_run(C.byref(P))
     if rc < 0:
         raise MemoryError("oracle allocation failed")
-    acc = acc_re + 1j * acc_im
+    acc = keep[-2] + 1j * keep[-1]
     return acc, T.source_spectrum(s, freqs, st.omega0, st.dt), rc
+
+
+def run_adjoint(st: Setup, nt: int, src, comp: int, rec, chans, freqs, A,
+                ckpt: int = 50, threads: int | None = None):
+    """Discrete adjoint of one source's run: returns d chi/d log(dt/eps_c)
+    on the padded grid [3][n3][n2][n1], for a misfit whose derivative with
+    respect to receiver sample u_n of item (rec, chan) is
+    sum_f Re(A[rec][chan][f] exp(i w'_f t_n))."""
+    lib = _load()
+    P, keep, _ = _build_params(st, nt, src, comp, rec, chans, freqs, threads)
+    A = np.asarray(A, dtype=np.complex128)
+    a_re = np.ascontiguousarray(A.real)
+    a_im = np.ascontiguousarray(A.imag)
+    n1, n2, n3 = st.n_pad
+    grad = np.zeros((3, n3, n2, n1))
+    rc = lib.oracle_gradient(C.byref(P), int(ckpt), _ptr(a_re), _ptr(a_im), _ptr(grad))
+    if rc < 0:
+        raise MemoryError("oracle allocation failed")
+    return grad
+
+
+def fold_padding(g_pad: np.ndarray, nbe: int) -> np.ndarray:
+    """Adjoint of the model extension (nearest-interior replication into the
+    padding): every padded cell's value is added to the interior cell it
+    copies.  [..., n3p, n2p, n1p] -> [..., n3, n2, n1]."""
+    out = g_pad
+    for ax in (-1, -2, -3):
+        out = np.moveaxis(out, ax, 0)
+        inner = out[nbe:out.shape[0] - nbe].copy()
+        inner[0] += out[:nbe].sum(axis=0)
+        inner[-1] += out[out.shape[0] - nbe:].sum(axis=0)
+        out = np.moveaxis(inner, 0, ax)
+    return out
+
+
+def misfit_gradient(w, G_obs, threads: int | None = None, nt: int | None = None,
+                    fpeak: float = 0.0, dt_override: float = 0.0, ckpt: int = 50,
+                    frozen: Setup | None = None, with_gradient: bool = True):
+    """chi = 1/2 sum over sources, receivers, channels, frequencies of
+    |log(G/G_obs)|^2 (real part: log-amplitude residual, imaginary part:
+    phase residual) and its gradient with respect to log sigma of every
+    input cell, for each of the three staggered conductivity arrays:
+    returns (chi, grad[3][n3][n2][n1], G).  dt, the step count and the CPML
+    tables are held fixed (pass `frozen`, the set-up of the reference model,
+    when evaluating perturbed models)."""
+    freqs = np.asarray(w.freqs, dtype=np.float64)
+    fp = T.peak_frequency(freqs, w.f0, fpeak)
+    st = make_setup(w, fp, dt_override, frozen)
+    if nt is None:
+        nt = w.nt if w.nt > 0 else T.auto_nt(freqs, w.f0, st.dt, fp)
+    chans = w.channels
+    chi = 0.0
+    g_pad = np.zeros((3,) + tuple(reversed(st.n_pad)))
+    G_all = np.zeros((len(w.sources), len(w.receivers), len(chans), len(freqs)), np.complex128)
+    for s_i, src in enumerate(w.sources):
+        comp = int(w.src_comp[s_i])
+        acc, S, _ = run_source(st, nt, src, comp, w.receivers, chans, freqs, threads)
+        G = green(acc, S, freqs, st.omega0, chans)
+        G_all[s_i] = G
+        r = np.log(G / G_obs[s_i])
+        chi += 0.5 * float(np.sum(np.abs(r) ** 2))
+        # d chi/d u_n = Re(sum_f conj(r_f) / acc_f * exp(i w'_f t_n))
+        if with_gradient:
+            A = np.conj(r) / acc
+            g_pad += run_adjoint(st, nt, src, comp, w.receivers, chans, freqs, A, ckpt, threads)
+    # d/d log(dt/eps) = d/d log rho = -d/d log sigma
+    return chi, -fold_padding(g_pad, st.nbe), G_all
 
 
 def green(acc, S, freqs, omega0, chans, moment: float = 1.0):

@@ -259,3 +259,240 @@ void oracle_curl_e(const oracle_params *p, const double *E1, const double *E2,
     curl_e(p, E1, E2, E3, c1, c2, c3, m, m + N, m + 2 * N, m + 3 * N, m + 4 * N, m + 5 * N);
     free(m);
 }
+
+/* ------------------------------------------------------------------------
+ * Discrete adjoint of oracle_run (reverse-mode differentiation written out
+ * by hand, FP64).  The misfit chi depends on the receiver DTFT values; its
+ * derivative with respect to the real sample u_n of item s is
+ *   dchi/du_n = sum_f Re( A[s][f] * exp(i w'_f t_n) ),
+ * with A supplied by the caller (for chi = 1/2 sum |log(G/G_obs)|^2 it is
+ * conj(r_f)/acc_f).  Output: grad[c][cell] = dchi/d log(dt/eps_c) on the
+ * padded grid = sum_n Ebar^{n+1} (E^{n+1} - E^n), because E^{n+1} - E^n is
+ * (dt/eps) times the curl term.  Forward states are recomputed per segment
+ * of `ckpt` steps from full-state checkpoints.
+ *
+ * Reverse of one step n (operations of the forward step in reverse order):
+ *   H update:  ebar_a = -/+ ch Hbar ;  CPML: psibar = b Q + ebar, ebar += a psibar,
+ *              Q = psibar ;  Ebar += (D+)^T ebar
+ *   records:   Ebar^{n+1} += w dchi/du (E channels), Hbar^{n+1/2} += w dchi/du (H)
+ *   E update:  grad += Ebar (E^{n+1} - E^n) ;  cbar = ce Ebar ; dbar from the
+ *              curl signs ; CPML as above ;  Hbar += (D-)^T dbar
+ * The transposes are gathers over the per-cell derivative adjoints:
+ *   ((D-)^T v)[i'] = sum_m cm[i' + r - 1 - m... ] -- written out below.
+ * ------------------------------------------------------------------------ */
+static void save_state(const double *buf, double *ck, size_t N) { memcpy(ck, buf, 18 * N * sizeof(double)); }
+
+/* forward step n on state buffer (same order and arithmetic as oracle_run,
+ * without the receiver records) */
+static void forward_step(const oracle_params *p, double *buf, int n)
+{
+    const int n1 = p->n1, n2 = p->n2, L = 2 * p->r;
+    const size_t N = (size_t)n1 * n2 * p->n3;
+    double *E1 = buf, *E2 = buf + N, *E3 = buf + 2 * N;
+    double *H1 = buf + 3 * N, *H2 = buf + 4 * N, *H3 = buf + 5 * N;
+    double *m = buf + 6 * N;                    /* 12 memory variables */
+    double *c1 = buf + 18 * N, *c2 = buf + 19 * N, *c3 = buf + 20 * N;
+    double *cH[3] = {c1, c2, c3};
+    curl_h(p, H1, H2, H3, c1, c2, c3, m, m + N, m + 2 * N, m + 3 * N, m + 4 * N, m + 5 * N);
+    {
+        double *cc = cH[p->src_comp];
+        const int *b = p->src_base;
+        for (int c = 0; c < L; c++)
+            for (int bb = 0; bb < L; bb++)
+                for (int a = 0; a < L; a++)
+                    cc[IDX(b[2] + c, b[1] + bb, b[0] + a)] -=
+                        p->wavelet[n] * p->src_q[(c * L + bb) * L + a];
+    }
+    update(p, E1, p->ce1, 0.0, c1, 1.0);
+    update(p, E2, p->ce2, 0.0, c2, 1.0);
+    update(p, E3, p->ce3, 0.0, c3, 1.0);
+    curl_e(p, E1, E2, E3, c1, c2, c3, m + 6 * N, m + 7 * N, m + 8 * N, m + 9 * N, m + 10 * N, m + 11 * N);
+    update(p, H1, NULL, p->ch, c1, -1.0);
+    update(p, H2, NULL, p->ch, c2, -1.0);
+    update(p, H3, NULL, p->ch, c3, -1.0);
+}
+
+/* CPML reverse for one derivative adjoint in place: psibar = b Q + dbar,
+ * dbar += a psibar, Q = psibar */
+static inline void cpml_rev(double *dbar, double *Q, double a, double b)
+{
+    double ps = b * (*Q) + *dbar;
+    *dbar += a * ps;
+    *Q = ps;
+}
+
+int oracle_gradient(const oracle_params *p, int ckpt, const double *A_re,
+                    const double *A_im, double *grad)
+{
+    const int n1 = p->n1, n2 = p->n2, n3 = p->n3, r = p->r, L = 2 * r, nb = p->nb;
+    const size_t N = (size_t)n1 * n2 * n3;
+    const int nt = p->nt, nf = p->nfreq;
+    const int nseg = (nt + ckpt - 1) / ckpt;
+    /* working state: 18 N (fields + memories) + 3 N curl scratch */
+    double *buf = calloc(21 * N, sizeof(double));
+    double *cks = calloc((size_t)nseg * 18 * N, sizeof(double));
+    double *seg = calloc((size_t)(ckpt + 1) * 3 * N, sizeof(double));   /* E^n of the segment */
+    /* adjoint: Eb[3], Hb[3], Q for the 6 E-step and 6 H-step memories, 6 derivative adjoints */
+    double *adj = calloc(24 * N, sizeof(double));
+    if (!buf || !cks || !seg || !adj) { free(buf); free(cks); free(seg); free(adj); return -1; }
+    double *Eb[3] = {adj, adj + N, adj + 2 * N}, *Hb[3] = {adj + 3 * N, adj + 4 * N, adj + 5 * N};
+    double *Qh = adj + 6 * N;     /* 6 arrays: adjoints of the curl-H memories */
+    double *Qe = adj + 12 * N;    /* 6 arrays: adjoints of the curl-E memories */
+    double *db = adj + 18 * N;    /* 6 arrays: derivative adjoints of the current half step */
+    memset(grad, 0, 3 * N * sizeof(double));
+
+    /* forward with checkpoints */
+    for (int n = 0; n < nt; n++) {
+        if (n % ckpt == 0) save_state(buf, cks + (size_t)(n / ckpt) * 18 * N, N);
+        forward_step(p, buf, n);
+    }
+    for (int sgi = nseg - 1; sgi >= 0; sgi--) {
+        const int n0 = sgi * ckpt, nend = (n0 + ckpt < nt) ? n0 + ckpt : nt;
+        memcpy(buf, cks + (size_t)sgi * 18 * N, 18 * N * sizeof(double));
+        memcpy(seg, buf, 3 * N * sizeof(double));
+        for (int n = n0; n < nend; n++) {
+            forward_step(p, buf, n);
+            memcpy(seg + (size_t)(n - n0 + 1) * 3 * N, buf, 3 * N * sizeof(double));
+        }
+        for (int n = nend - 1; n >= n0; n--) {
+            const double *En = seg + (size_t)(n - n0) * 3 * N;        /* E^n */
+            const double *En1 = seg + (size_t)(n - n0 + 1) * 3 * N;   /* E^{n+1} */
+            /* --- reverse of the H update: derivative adjoints of curl E --- */
+            memset(db, 0, 6 * N * sizeof(double));
+#pragma omp parallel for num_threads(p->nthreads) schedule(static)
+            for (int k = r; k <= n3 - 1 - r; k++)
+                for (int j = r; j <= n2 - 1 - r; j++)
+                    for (int i = r; i <= n1 - 1 - r; i++) {
+                        size_t id = IDX(k, j, i);
+                        /* order: D2E3, D3E2, D3E1, D1E3, D1E2, D2E1 */
+                        double d[6] = {-p->ch * Hb[0][id], p->ch * Hb[0][id],
+                                       -p->ch * Hb[1][id], p->ch * Hb[1][id],
+                                       -p->ch * Hb[2][id], p->ch * Hb[2][id]};
+                        if (in_slab(j, n2, nb)) {
+                            cpml_rev(&d[0], &Qe[0 * N + id], p->a2h[j], p->b2h[j]);
+                            cpml_rev(&d[5], &Qe[5 * N + id], p->a2h[j], p->b2h[j]);
+                        }
+                        if (in_slab(k, n3, nb)) {
+                            cpml_rev(&d[1], &Qe[1 * N + id], p->a3h[k], p->b3h[k]);
+                            cpml_rev(&d[2], &Qe[2 * N + id], p->a3h[k], p->b3h[k]);
+                        }
+                        if (in_slab(i, n1, nb)) {
+                            cpml_rev(&d[3], &Qe[3 * N + id], p->a1h[i], p->b1h[i]);
+                            cpml_rev(&d[4], &Qe[4 * N + id], p->a1h[i], p->b1h[i]);
+                        }
+                        for (int q = 0; q < 6; q++) db[q * N + id] = d[q];
+                    }
+            /* Ebar += (D+)^T dbar: e_{D2E3}[j] = sum_m cp2[j][m] E3[j-r+1+m], so
+             * E3[j'] receives cp2[j][m] dbar[j] for every (j, m) with
+             * j - r + 1 + m = j', i.e. j = j' + r - 1 - m. */
+#pragma omp parallel for num_threads(p->nthreads) schedule(static)
+            for (int k = 0; k < n3; k++)
+                for (int j = 0; j < n2; j++)
+                    for (int i = 0; i < n1; i++) {
+                        size_t id = IDX(k, j, i);
+                        double e1 = 0, e2 = 0, e3 = 0;
+                        for (int m2 = 0; m2 < L; m2++) {
+                            int jj = j + r - 1 - m2, kk = k + r - 1 - m2, ii = i + r - 1 - m2;
+                            if (jj >= r && jj <= n2 - 1 - r) {
+                                double c = p->cp2[jj * L + m2];
+                                e3 += c * db[0 * N + IDX(k, jj, i)];     /* D2E3 */
+                                e1 += c * db[5 * N + IDX(k, jj, i)];     /* D2E1 */
+                            }
+                            if (kk >= r && kk <= n3 - 1 - r) {
+                                double c = p->cp3[kk * L + m2];
+                                e2 += c * db[1 * N + IDX(kk, j, i)];     /* D3E2 */
+                                e1 += c * db[2 * N + IDX(kk, j, i)];     /* D3E1 */
+                            }
+                            if (ii >= r && ii <= n1 - 1 - r) {
+                                double c = p->cp1[ii * L + m2];
+                                e3 += c * db[3 * N + IDX(k, j, ii)];     /* D1E3 */
+                                e2 += c * db[4 * N + IDX(k, j, ii)];     /* D1E2 */
+                            }
+                        }
+                        Eb[0][id] += e1;
+                        Eb[1][id] += e2;
+                        Eb[2][id] += e3;
+                    }
+            /* --- records: E^{n+1} at stamp (n+1) dt, H^{n+1/2} at (n+1/2) dt --- */
+            for (int ir = 0; ir < p->nrec; ir++)
+                for (int ic = 0; ic < p->nchan; ic++) {
+                    int ch = p->chan[ic];
+                    size_t s = (size_t)ir * p->nchan + ic;
+                    const double *pr = ch < 3 ? p->phE_re : p->phH_re;
+                    const double *pi = ch < 3 ? p->phE_im : p->phH_im;
+                    double g = 0.0;
+                    for (int f = 0; f < nf; f++)
+                        g += A_re[s * nf + f] * pr[(size_t)n * nf + f] - A_im[s * nf + f] * pi[(size_t)n * nf + f];
+                    double *F = ch < 3 ? Eb[ch] : Hb[ch - 3];
+                    const int *b = p->rec_base + 3 * s;
+                    const double *w = p->rec_w + s * L * L * L;
+                    for (int c = 0; c < L; c++)
+                        for (int bb = 0; bb < L; bb++)
+                            for (int a = 0; a < L; a++)
+                                F[IDX(b[2] + c, b[1] + bb, b[0] + a)] += w[(c * L + bb) * L + a] * g;
+                }
+            /* --- reverse of the E update --- */
+            memset(db, 0, 6 * N * sizeof(double));
+#pragma omp parallel for num_threads(p->nthreads) schedule(static)
+            for (int k = r; k <= n3 - 1 - r; k++)
+                for (int j = r; j <= n2 - 1 - r; j++)
+                    for (int i = r; i <= n1 - 1 - r; i++) {
+                        size_t id = IDX(k, j, i);
+                        for (int c = 0; c < 3; c++)
+                            grad[c * N + id] += Eb[c][id] * (En1[c * N + id] - En[c * N + id]);
+                        double cb1 = p->ce1[id] * Eb[0][id], cb2 = p->ce2[id] * Eb[1][id],
+                               cb3 = p->ce3[id] * Eb[2][id];
+                        /* order: D2H3, D3H2, D3H1, D1H3, D1H2, D2H1 */
+                        double d[6] = {cb1, -cb1, cb2, -cb2, cb3, -cb3};
+                        if (in_slab(j, n2, nb)) {
+                            cpml_rev(&d[0], &Qh[0 * N + id], p->a2i[j], p->b2i[j]);
+                            cpml_rev(&d[5], &Qh[5 * N + id], p->a2i[j], p->b2i[j]);
+                        }
+                        if (in_slab(k, n3, nb)) {
+                            cpml_rev(&d[1], &Qh[1 * N + id], p->a3i[k], p->b3i[k]);
+                            cpml_rev(&d[2], &Qh[2 * N + id], p->a3i[k], p->b3i[k]);
+                        }
+                        if (in_slab(i, n1, nb)) {
+                            cpml_rev(&d[3], &Qh[3 * N + id], p->a1i[i], p->b1i[i]);
+                            cpml_rev(&d[4], &Qh[4 * N + id], p->a1i[i], p->b1i[i]);
+                        }
+                        for (int q = 0; q < 6; q++) db[q * N + id] = d[q];
+                    }
+            /* Hbar += (D-)^T dbar: d_{D2H3}[j] = sum_m cm2[j][m] H3[j-r+m], so
+             * H3[j'] receives cm2[j][m] dbar[j] for j = j' + r - m. */
+#pragma omp parallel for num_threads(p->nthreads) schedule(static)
+            for (int k = 0; k < n3; k++)
+                for (int j = 0; j < n2; j++)
+                    for (int i = 0; i < n1; i++) {
+                        size_t id = IDX(k, j, i);
+                        double h1 = 0, h2 = 0, h3 = 0;
+                        for (int m2 = 0; m2 < L; m2++) {
+                            int jj = j + r - m2, kk = k + r - m2, ii = i + r - m2;
+                            if (jj >= r && jj <= n2 - 1 - r) {
+                                double c = p->cm2[jj * L + m2];
+                                h3 += c * db[0 * N + IDX(k, jj, i)];     /* D2H3 */
+                                h1 += c * db[5 * N + IDX(k, jj, i)];     /* D2H1 */
+                            }
+                            if (kk >= r && kk <= n3 - 1 - r) {
+                                double c = p->cm3[kk * L + m2];
+                                h2 += c * db[1 * N + IDX(kk, j, i)];     /* D3H2 */
+                                h1 += c * db[2 * N + IDX(kk, j, i)];     /* D3H1 */
+                            }
+                            if (ii >= r && ii <= n1 - 1 - r) {
+                                double c = p->cm1[ii * L + m2];
+                                h3 += c * db[3 * N + IDX(k, j, ii)];     /* D1H3 */
+                                h2 += c * db[4 * N + IDX(k, j, ii)];     /* D1H2 */
+                            }
+                        }
+                        Hb[0][id] += h1;
+                        Hb[1][id] += h2;
+                        Hb[2][id] += h3;
+                    }
+        }
+    }
+    free(buf);
+    free(cks);
+    free(seg);
+    free(adj);
+    return 0;
+}
