@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--cube-n", type=int, default=400)
     ap.add_argument("--rd", type=int, default=0, help="override the stencil half length")
     ap.add_argument("--nt", type=int, default=0, help="override the time-step count")
+    ap.add_argument("--graph", type=int, default=0, help="time steps per captured hipGraph")
+    ap.add_argument("--tile-kz", type=int, default=-1, help="z planes per block (-1: autotuned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -98,7 +100,8 @@ def main():
         w = w.with_(nt=args.nt)
     log(f"[bench] workload {w.name} padded cells {w.padded_cells}")
 
-    model = emm.Model(w, profile=1)
+    model = emm.Model(w, profile=0 if args.graph else 1, graph_steps=args.graph,
+                      tile_kz=args.tile_kz)
     for i in range(args.warmup):
         model.forward()
         log(f"[bench] warmup {i} done")
@@ -121,8 +124,8 @@ def main():
     cells = info["cells"]
     ms_per_step = wall / args.steps * 1e3
     value = cells * nt * args.steps / wall / 1e9
-    e_avg_s = e_ms / e_n / 1e3
-    h_avg_s = h_ms / h_n / 1e3
+    e_avg_s = e_ms / e_n / 1e3 if e_n else float("nan")
+    h_avg_s = h_ms / h_n / 1e3 if h_n else float("nan")
     achieved = info["e_bytes"] / e_avg_s / 1e9
     log(f"[bench] nt={nt} wall/forward={ms_per_step:.1f} ms device loop/forward="
         f"{dev_ms / args.steps:.1f} ms e_step avg={e_avg_s * 1e6:.2f} us "

@@ -75,7 +75,13 @@ typedef struct {
     double wavelet_fpeak;  /* source wavelet peak frequency; 0 = 2 sqrt(f_max f0) [0] */
     int    allow_unstable; /* test hook: accept dt_override above the CFL limit [0] */
     int    profile;        /* 1 = time every stencil launch with HIP events (emm_query) [0] */
-    int    tile_kz;        /* z planes per thread block; 0 = chosen from the grid [0] */
+    int    tile_kz;        /* z planes per thread block; 0 = chosen from the grid, -1 = autotuned
+                              on the first forward (timing candidates on this model) [0] */
+    int    checkpoint_every; /* > 0: emm_forward keeps full-state checkpoints every this many
+                              steps for a following emm_gradient; emm_gradient's interval
+                              (0 = 50) [0] */
+    int    graph_steps;    /* > 0: capture this many time steps in one hipGraph and replay it
+                              (a device step counter advances between replays) [0] */
 } emm_options;
 
 /* A point electric dipole (Section 5, "Survey acquisitions"): position in
@@ -128,6 +134,32 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc,
                        const emm_receiver *rec, int nrec, unsigned chan_mask,
                        const double *freq_hz, int nfreq, double *green,
                        void *hip_stream);
+
+/* Discrete adjoint of the whole time loop (the exact gradient of the
+ * FP32 time stepping as written: reverse of every E and H update with the
+ * transposed finite-difference operators, reverse of the CPML memory-variable
+ * recursion, reverse of the receiver DTFT), evaluated with full-state
+ * checkpoints every checkpoint_every steps and forward recomputation inside
+ * each segment.  The scalar L is either
+ *   g_obs != NULL: L = 1/2 sum over all results of |log(G/G_obs)|^2 (real
+ *                  part: log-amplitude residual, imaginary part: phase
+ *                  residual), returned in *misfit (may be NULL), or
+ *   g_bar != NULL: any L given by its cotangent dL/dRe G + i dL/dIm G;
+ * both laid out like `green`; exactly one must be given.  Output
+ *   grad[(c*n3 + k)*n2 + j)*n1 + i] = dL/d log sigma_c at input cell (i,j,k),
+ *   c = 0, 1, 2 for the conductivities behind rho11, rho22, rho33,
+ * summed over sources (3*n1*n2*n3 doubles, caller-owned), with dt, the step
+ * count and the CPML profile held fixed (they depend on the largest
+ * resistivities).  green (may be NULL) receives G.  If the previous
+ * emm_forward on this model ran with checkpoint_every > 0 and the same
+ * acquisition, its checkpoints are reused; otherwise the forward is run here.
+ * This is the gradient that CSEM inversion needs (the paper's stated
+ * horizon, Section 9).  Errors: as emm_forward, plus ARG. */
+emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc,
+                        const emm_receiver *rec, int nrec, unsigned chan_mask,
+                        const double *freq_hz, int nfreq, const double *g_obs,
+                        const double *g_bar, double *green, double *misfit,
+                        double *grad, void *hip_stream);
 
 /* Free device and host memory. NULL-safe. */
 void emm_destroy(emm_model *m);

@@ -11,7 +11,7 @@ import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
-SOURCES = ["csrc/emm_api.cpp", "csrc/emm_setup.cpp", "csrc/emm_kernels.hip"]
+SOURCES = ["csrc/emm_api.cpp", "csrc/emm_setup.cpp", "csrc/emm_kernels.hip", "csrc/emm_adjoint.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("EMM_OFFLOAD_ARCH", "gfx950")
 

@@ -8,10 +8,12 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
 
+#include "emm_adjoint.h"
 #include "emm_internal.h"
 #include "emm_setup.h"
 
@@ -28,6 +30,26 @@ struct DevBuf {
 };
 
 }  // namespace
+
+// Host-side description of the acquisition of the last forward run and the
+// kernel parameters built for it.
+struct Acq {
+    int nsrc = 0, nrec = 0, nch = 0, nf = 0, nt = 0;
+    unsigned chan_mask = 0;
+    std::vector<emm_source> src;
+    std::vector<emm_receiver> rec;
+    std::vector<double> freqs;
+    std::vector<int> chans;
+    std::vector<double> sscale;                     // source amplitude scale
+    std::vector<std::complex<double>> Shat, wp;     // source spectrum, omega'
+    // receiver items {src, field, bx, by, bz, slot} and their weights wx|wy|wz:
+    // H channels are sampled in the E-step launch, E channels in the H-step one
+    std::vector<int> items_estep, items_hstep;
+    std::vector<float> w_estep, w_hstep;
+    emm::StepParams Pe{}, Ph{};
+    int ckpt = 0;                                   // checkpoint interval of the stored run (0: none)
+    bool valid = false;
+};
 
 struct emm_model {
     emm_options opt{};
@@ -46,6 +68,13 @@ struct emm_model {
     float *tab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // cmx cmy cmz cpx cpy cpz
     // forward-lifetime device data (grown on demand, kept between forwards)
     DevBuf fields, psi, acc, cpml, srcinfo, srcq, wav, items, itemw, phase;
+    DevBuf ckpts;                                   // full-state checkpoints of the last run
+    DevBuf stepdev;                                 // device step counter of graph replays
+    // adjoint: Et|Hb fields, Q (12 slab arrays), T (6), E snapshots, per-source
+    // gradients, transposed tables, injection lists and coefficients
+    DevBuf adjf, adjq, adjt, snaps, grad, tabT, inj, injA, adjcpml;
+    Acq acq;
+    std::map<int, int> tuned_kz;                    // autotuned z chunk per source count
     hipEvent_t ev_loop[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ring;       // profiling: start/end pairs
     emm_info info{};
@@ -105,6 +134,10 @@ void step_bytes(const emm_model *m, double &eb, double &hb) {
 int choose_kz(const emm_model *m, int xt, int yt, int nsrc) {
     const int nzv = m->np[2] - 2 * m->r;
     if (m->opt.tile_kz > 0) return std::min(m->opt.tile_kz, nzv);
+    if (m->opt.tile_kz < 0) {
+        auto it = m->tuned_kz.find(nsrc);
+        if (it != m->tuned_kz.end()) return it->second;
+    }
     const long long per_chunk = (long long)xt * yt * nsrc;
     long long zc = std::max<long long>(1, (4096 + per_chunk - 1) / per_chunk);
     zc = std::min<long long>(zc, std::max(1, nzv / 8));
@@ -133,6 +166,8 @@ emm_status emm_default_options(emm_options *o) {
     o->allow_unstable = 0;
     o->profile = 0;
     o->tile_kz = 0;
+    o->checkpoint_every = 0;
+    o->graph_steps = 0;
     return EMM_OK;
 }
 
@@ -164,7 +199,8 @@ void emm_destroy(emm_model *m) {
     for (float *p : m->ce) if (p) (void)hipFree(p);
     for (float *p : m->tab) if (p) (void)hipFree(p);
     for (DevBuf *b : {&m->fields, &m->psi, &m->acc, &m->cpml, &m->srcinfo, &m->srcq, &m->wav,
-                      &m->items, &m->itemw, &m->phase})
+                      &m->items, &m->itemw, &m->phase, &m->ckpts, &m->adjf, &m->adjq, &m->adjt,
+                      &m->snaps, &m->grad, &m->tabT, &m->inj, &m->injA, &m->adjcpml, &m->stepdev})
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : m->ev_loop) if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : m->ring) if (e) (void)hipEventDestroy(e);
@@ -188,7 +224,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (opt.nb < 0) return fail(nullptr, EMM_ERR_ARG, "nb must be >= 0");
     if (!(opt.f0 > 0.0) || !std::isfinite(opt.f0)) return fail(nullptr, EMM_ERR_ARG, "f0 must be > 0");
     if (!(opt.cfl > 0.0) || !std::isfinite(opt.cfl)) return fail(nullptr, EMM_ERR_ARG, "cfl must be > 0");
-    if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < 0 ||
+    if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -331,31 +367,54 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     return EMM_OK;
 }
 
-emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_receiver *rec,
-                       int nrec, unsigned chan_mask, const double *freq_hz, int nfreq,
-                       double *green, void *hip_stream) {
-    if (!m) return fail(nullptr, EMM_ERR_ARG, "NULL model");
-    m->err.clear();
-    if (!src || !rec || !green || nsrc < 1 || nrec < 1 || chan_mask == 0 || (chan_mask & ~0x3Fu))
-        return fail(m, EMM_ERR_ARG, "bad sources, receivers, output pointer or channel mask");
+}  // extern "C"
+
+namespace {
+
+// staggering (half along x, y, z) of Ex, Ey, Ez, Hx, Hy, Hz
+const int kStag[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+
+bool same_acquisition(const Acq &a, const emm_source *src, int nsrc, const emm_receiver *rec,
+                      int nrec, unsigned chan_mask, const double *freq, int nfreq) {
+    if (!a.valid || a.nsrc != nsrc || a.nrec != nrec || a.chan_mask != chan_mask || a.nf != nfreq)
+        return false;
+    for (int s = 0; s < nsrc; ++s)
+        if (a.src[s].x != src[s].x || a.src[s].y != src[s].y || a.src[s].z != src[s].z ||
+            a.src[s].comp != src[s].comp || a.src[s].moment != src[s].moment)
+            return false;
+    for (int i = 0; i < nrec; ++i)
+        if (a.rec[i].x != rec[i].x || a.rec[i].y != rec[i].y || a.rec[i].z != rec[i].z) return false;
+    for (int f = 0; f < nfreq; ++f)
+        if (a.freqs[f] != freq[f]) return false;
+    return true;
+}
+
+// Validate the acquisition, build the host tables (stencils, wavelet, DTFT
+// phases, CPML), upload them and fill the kernel parameters (Sections 3.1,
+// 3.4, 3.5; see emm_forward in emm.h).
+emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_receiver *rec, int nrec,
+                   unsigned chan_mask, const double *freq_hz, int nfreq, hipStream_t stream) {
+    Acq &A = m->acq;
+    A.valid = false;
+    A.ckpt = 0;
+    if (!src || !rec || nsrc < 1 || nrec < 1 || chan_mask == 0 || (chan_mask & ~0x3Fu))
+        return fail(m, EMM_ERR_ARG, "bad sources, receivers or channel mask");
     if (!freq_hz || nfreq < 1) return fail(m, EMM_ERR_FREQ, "need at least one frequency");
     for (int f = 0; f < nfreq; ++f)
         if (!(freq_hz[f] > 0.0) || !std::isfinite(freq_hz[f]))
             return fail(m, EMM_ERR_FREQ, "frequencies must be finite and > 0");
     const int r = m->r, L = 2 * r, L3 = L * L * L;
-    std::vector<int> chans;
+    A.chans.clear();
     for (int c = 0; c < 6; ++c)
-        if (chan_mask >> c & 1u) chans.push_back(c);
-    const int nch = (int)chans.size();
-    // staggering (half along x, y, z) of Ex, Ey, Ez, Hx, Hy, Hz
-    static const int stag[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+        if (chan_mask >> c & 1u) A.chans.push_back(c);
+    const int nch = (int)A.chans.size();
     auto coords = [&](int a, int h) -> const std::vector<double> & { return h ? m->half[a] : m->axes[a]; };
     auto inside = [&](int a, int base) { return base >= m->nbe && base + L - 1 <= m->np[a] - 1 - m->nbe; };
 
     // sources: (2r)^3 stencil on the E_comp grid, J = moment w / V, scaled to max |q| = 1
     std::vector<int> sinfo(4 * nsrc);
     std::vector<float> sq((size_t)nsrc * L3);
-    std::vector<double> sscale(nsrc);
+    A.sscale.assign(nsrc, 1.0);
     for (int s = 0; s < nsrc; ++s) {
         const emm_source &S = src[s];
         if (S.comp < 0 || S.comp > 2 || !std::isfinite(S.moment) || S.moment == 0.0 ||
@@ -385,30 +444,32 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
                     qd[(c * L + b) * L + a] = v;
                     qmax = std::max(qmax, std::fabs(v));
                 }
-        sscale[s] = 1.0 / qmax;
-        for (int q = 0; q < L3; ++q) sq[(size_t)s * L3 + q] = (float)(qd[q] * sscale[s]);
+        A.sscale[s] = 1.0 / qmax;
+        for (int q = 0; q < L3; ++q) sq[(size_t)s * L3 + q] = (float)(qd[q] * A.sscale[s]);
         sinfo[4 * s] = S.comp;
         sinfo[4 * s + 1] = base[0];
         sinfo[4 * s + 2] = base[1];
         sinfo[4 * s + 3] = base[2];
     }
     // receiver items: E channels in the H-step launch, H channels in the E-step launch
-    std::vector<int> info_e, info_h;     // {src, field, bx, by, bz, slot}
-    std::vector<float> w_e, w_h;
+    A.items_estep.clear();
+    A.items_hstep.clear();
+    A.w_estep.clear();
+    A.w_hstep.clear();
     for (int i = 0; i < nrec; ++i) {
         const double p[3] = {rec[i].x, rec[i].y, rec[i].z};
         if (!std::isfinite(p[0]) || !std::isfinite(p[1]) || !std::isfinite(p[2]))
             return fail(m, EMM_ERR_ARG, "receiver position not finite");
         for (int c = 0; c < nch; ++c) {
-            const int ch = chans[c];
+            const int ch = A.chans[c];
             double w[3][2 * emm::kMaxR];
             int base[3];
             for (int a = 0; a < 3; ++a) {
-                base[a] = emm::point_stencil(coords(a, stag[ch][a]), p[a], r, w[a]);
+                base[a] = emm::point_stencil(coords(a, kStag[ch][a]), p[a], r, w[a]);
                 if (!inside(a, base[a])) return fail(m, EMM_ERR_GEOMETRY, "receiver stencil leaves the interior");
             }
-            std::vector<int> &inf = ch < 3 ? info_h : info_e;   // E channels -> H-step launch
-            std::vector<float> &wv = ch < 3 ? w_h : w_e;
+            std::vector<int> &inf = ch < 3 ? A.items_hstep : A.items_estep;
+            std::vector<float> &wv = ch < 3 ? A.w_hstep : A.w_estep;
             for (int s = 0; s < nsrc; ++s) {
                 const int slot = (s * nrec + i) * nch + c;
                 inf.insert(inf.end(), {s, ch % 3, base[0], base[1], base[2], slot});
@@ -417,10 +478,6 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
             }
         }
     }
-    // recorded in the H step: E^{n+1}; in the E step: H^{n+1/2}
-    std::vector<int> &items_hstep = info_h;  // holds E channels
-    std::vector<int> &items_estep = info_e;  // holds H channels
-    std::vector<float> &wts_hstep = w_h, &wts_estep = w_e;
 
     // time axis, wavelet, DTFT phases, CPML
     double fmax = 0.0, fmin = 1e300;
@@ -438,14 +495,15 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     }
     const std::vector<double> sw = emm::wavelet(nt, m->dt, fp);
     std::vector<float> swf(sw.begin(), sw.end());
-    std::vector<std::complex<double>> Shat(nfreq, 0.0), wp(nfreq);
+    A.Shat.assign(nfreq, 0.0);
+    A.wp.assign(nfreq, 0.0);
     std::vector<double2> ph((size_t)2 * nt * nfreq);   // [0]: E-step (H stamps), [1]: H-step (E stamps)
     for (int f = 0; f < nfreq; ++f) {
-        wp[f] = emm::omega_prime(freq_hz[f], m->omega0);
+        A.wp[f] = emm::omega_prime(freq_hz[f], m->omega0);
         for (int n = 0; n < nt; ++n) {
-            const std::complex<double> zh = std::exp(std::complex<double>(0, 1) * wp[f] * ((n + 0.5) * m->dt));
-            const std::complex<double> ze = std::exp(std::complex<double>(0, 1) * wp[f] * ((n + 1.0) * m->dt));
-            Shat[f] += (double)swf[n] * zh;
+            const std::complex<double> zh = std::exp(std::complex<double>(0, 1) * A.wp[f] * ((n + 0.5) * m->dt));
+            const std::complex<double> ze = std::exp(std::complex<double>(0, 1) * A.wp[f] * ((n + 1.0) * m->dt));
+            A.Shat[f] += (double)swf[n] * zh;
             ph[(size_t)n * nfreq + f] = make_double2(zh.real(), zh.imag());
             ph[(size_t)nt * nfreq + (size_t)n * nfreq + f] = make_double2(ze.real(), ze.imag());
         }
@@ -468,7 +526,6 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     // device buffers
     emm_status st;
     HIP_OK(m, hipSetDevice(m->device));
-    hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
     const long long plane = (long long)m->pitch * m->np[1];
     const long long fstride = plane * m->np[2];
     const int nb = m->nb;
@@ -485,9 +542,9 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     if ((st = ensure(m, m->srcinfo, sinfo.size() * sizeof(int))) != EMM_OK) return st;
     if ((st = ensure(m, m->srcq, sq.size() * sizeof(float))) != EMM_OK) return st;
     if ((st = ensure(m, m->wav, swf.size() * sizeof(float))) != EMM_OK) return st;
-    const size_t ni_e = items_estep.size() / 6, ni_h = items_hstep.size() / 6;
-    if ((st = ensure(m, m->items, (items_estep.size() + items_hstep.size()) * sizeof(int))) != EMM_OK) return st;
-    if ((st = ensure(m, m->itemw, (wts_estep.size() + wts_hstep.size()) * sizeof(float))) != EMM_OK) return st;
+    const size_t ni_e = A.items_estep.size() / 6, ni_h = A.items_hstep.size() / 6;
+    if ((st = ensure(m, m->items, (A.items_estep.size() + A.items_hstep.size()) * sizeof(int))) != EMM_OK) return st;
+    if ((st = ensure(m, m->itemw, (A.w_estep.size() + A.w_hstep.size()) * sizeof(float))) != EMM_OK) return st;
     if ((st = ensure(m, m->phase, ph.size() * sizeof(double2))) != EMM_OK) return st;
 
     char *items_d = (char *)m->items.p;
@@ -496,20 +553,19 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     HIP_OK(m, hipMemcpyAsync(m->srcinfo.p, sinfo.data(), sinfo.size() * sizeof(int), hipMemcpyHostToDevice, stream));
     HIP_OK(m, hipMemcpyAsync(m->srcq.p, sq.data(), sq.size() * sizeof(float), hipMemcpyHostToDevice, stream));
     HIP_OK(m, hipMemcpyAsync(m->wav.p, swf.data(), swf.size() * sizeof(float), hipMemcpyHostToDevice, stream));
-    if (!items_estep.empty())
-        HIP_OK(m, hipMemcpyAsync(items_d, items_estep.data(), items_estep.size() * sizeof(int), hipMemcpyHostToDevice, stream));
-    if (!items_hstep.empty())
-        HIP_OK(m, hipMemcpyAsync(items_d + items_estep.size() * sizeof(int), items_hstep.data(),
-                                 items_hstep.size() * sizeof(int), hipMemcpyHostToDevice, stream));
-    if (!wts_estep.empty())
-        HIP_OK(m, hipMemcpyAsync(itemw_d, wts_estep.data(), wts_estep.size() * sizeof(float), hipMemcpyHostToDevice, stream));
-    if (!wts_hstep.empty())
-        HIP_OK(m, hipMemcpyAsync(itemw_d + wts_estep.size() * sizeof(float), wts_hstep.data(),
-                                 wts_hstep.size() * sizeof(float), hipMemcpyHostToDevice, stream));
+    if (!A.items_estep.empty())
+        HIP_OK(m, hipMemcpyAsync(items_d, A.items_estep.data(), A.items_estep.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+    if (!A.items_hstep.empty())
+        HIP_OK(m, hipMemcpyAsync(items_d + A.items_estep.size() * sizeof(int), A.items_hstep.data(),
+                                 A.items_hstep.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+    if (!A.w_estep.empty())
+        HIP_OK(m, hipMemcpyAsync(itemw_d, A.w_estep.data(), A.w_estep.size() * sizeof(float), hipMemcpyHostToDevice, stream));
+    if (!A.w_hstep.empty())
+        HIP_OK(m, hipMemcpyAsync(itemw_d + A.w_estep.size() * sizeof(float), A.w_hstep.data(),
+                                 A.w_hstep.size() * sizeof(float), hipMemcpyHostToDevice, stream));
     HIP_OK(m, hipMemcpyAsync(m->phase.p, ph.data(), ph.size() * sizeof(double2), hipMemcpyHostToDevice, stream));
-    HIP_OK(m, hipMemsetAsync(m->fields.p, 0, (size_t)6 * nsrc * fstride * sizeof(float), stream));
-    if (nb) HIP_OK(m, hipMemsetAsync(m->psi.p, 0, (size_t)nsrc * ps_per_src * sizeof(float), stream));
-    HIP_OK(m, hipMemsetAsync(m->acc.p, 0, (size_t)nslot * nfreq * acc_elem, stream));
+    // the host vectors above die with this call: wait for the copies
+    HIP_OK(m, hipStreamSynchronize(stream));
 
     // kernel parameters
     emm::StepParams P{};
@@ -527,13 +583,13 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     P.nsrc = nsrc;
     P.nstencil = P.xt * P.yt * P.zc * nsrc;
     float *F = (float *)m->fields.p;
+    // per-source field arrays are laid out [comp][src][...]: source s at + s * fstride
     P.E1 = F;
     P.E2 = F + (size_t)nsrc * fstride;
     P.E3 = F + (size_t)2 * nsrc * fstride;
     P.H1 = F + (size_t)3 * nsrc * fstride;
     P.H2 = F + (size_t)4 * nsrc * fstride;
     P.H3 = F + (size_t)5 * nsrc * fstride;
-    // per-source field arrays are interleaved as [comp][src][...]: source s at + s * fstride
     P.ce1 = m->ce[0];
     P.ce2 = m->ce[1];
     P.ce3 = m->ce[2];
@@ -592,12 +648,72 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     Pe.phase = (const double2 *)m->phase.p;
     Pe.nrecblk = (int)((ni_e + waves - 1) / waves + 7) / 8 * 8;
     Ph.nitems = (int)ni_h;
-    Ph.item_info = (const int *)(items_d + items_estep.size() * sizeof(int));
-    Ph.item_w = (const float *)(itemw_d + wts_estep.size() * sizeof(float));
+    Ph.item_info = (const int *)(items_d + A.items_estep.size() * sizeof(int));
+    Ph.item_w = (const float *)(itemw_d + A.w_estep.size() * sizeof(float));
     Ph.phase = (const double2 *)m->phase.p + (size_t)nt * nfreq;
     Ph.nrecblk = (int)((ni_h + waves - 1) / waves + 7) / 8 * 8;
+    A.Pe = Pe;
+    A.Ph = Ph;
+    A.nsrc = nsrc;
+    A.nrec = nrec;
+    A.nch = nch;
+    A.nf = nfreq;
+    A.nt = nt;
+    A.chan_mask = chan_mask;
+    A.src.assign(src, src + nsrc);
+    A.rec.assign(rec, rec + nrec);
+    A.freqs.assign(freq_hz, freq_hz + nfreq);
+    A.valid = true;
+    return EMM_OK;
+}
 
-    // time loop: per step E step (+ H-channel DTFT) then H step (+ E-channel DTFT)
+emm_status autotune(emm_model *m, hipStream_t stream);
+
+// bytes of one source's full time-stepping state (fields + CPML memories)
+size_t state_floats(const emm_model *m) {
+    const long long plane = (long long)m->pitch * m->np[1];
+    const long long fstride = plane * m->np[2];
+    const int nb = m->nb;
+    const long long psxs = nb ? (long long)m->np[2] * m->np[1] * 2 * nb : 0;
+    const long long psys = nb ? (long long)m->np[2] * 2 * nb * m->pitch : 0;
+    const long long pszs = nb ? (long long)2 * nb * plane : 0;
+    return (size_t)(6 * fstride + 4 * (psxs + psys + pszs));
+}
+
+// Checkpoint c <-> live state copies (fields and CPML memories of all sources).
+emm_status copy_state(emm_model *m, int c, bool save, hipStream_t stream) {
+    const Acq &A = m->acq;
+    const size_t ff = (size_t)6 * A.nsrc * A.Pe.fstride * sizeof(float);
+    const size_t pf = state_floats(m) * A.nsrc * sizeof(float) - ff;
+    char *ck = (char *)m->ckpts.p + (size_t)c * (ff + pf);
+    if (save) {
+        HIP_OK(m, hipMemcpyAsync(ck, m->fields.p, ff, hipMemcpyDeviceToDevice, stream));
+        if (pf) HIP_OK(m, hipMemcpyAsync(ck + ff, m->psi.p, pf, hipMemcpyDeviceToDevice, stream));
+    } else {
+        HIP_OK(m, hipMemcpyAsync(m->fields.p, ck, ff, hipMemcpyDeviceToDevice, stream));
+        if (pf) HIP_OK(m, hipMemcpyAsync(m->psi.p, ck + ff, pf, hipMemcpyDeviceToDevice, stream));
+    }
+    return EMM_OK;
+}
+
+// Zero the state and run all time steps: per step the E step (+ H-channel
+// DTFT) then the H step (+ E-channel DTFT).  ckpt > 0 stores the full state
+// before every step n with n % ckpt == 0.
+emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
+    Acq &A = m->acq;
+    emm_status st;
+    const int nsrc = A.nsrc, nt = A.nt, r = m->r;
+    const long long fstride = A.Pe.fstride;
+    const size_t acc_elem = m->opt.dft_mode ? sizeof(float4) : sizeof(double2);
+    const int nslot = A.nsrc * A.nrec * A.nch;
+    HIP_OK(m, hipMemsetAsync(m->fields.p, 0, (size_t)6 * nsrc * fstride * sizeof(float), stream));
+    const size_t psi_bytes = (state_floats(m) - 6 * fstride) * nsrc * sizeof(float);
+    if (psi_bytes) HIP_OK(m, hipMemsetAsync(m->psi.p, 0, psi_bytes, stream));
+    HIP_OK(m, hipMemsetAsync(m->acc.p, 0, (size_t)nslot * A.nf * acc_elem, stream));
+    if (ckpt > 0) {
+        const int nck = (nt + ckpt - 1) / ckpt;
+        if ((st = ensure(m, m->ckpts, (size_t)nck * state_floats(m) * nsrc * sizeof(float))) != EMM_OK) return st;
+    }
     const bool prof = m->opt.profile != 0;
     const int ring_pairs = 128;
     if (prof && m->ring.empty()) {
@@ -619,18 +735,54 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
         return EMM_OK;
     };
     HIP_OK(m, hipEventRecord(m->ev_loop[0], stream));
-    for (int n = 0; n < nt; ++n) {
+    int n_begin = 0;
+    // K steps per captured hipGraph, replayed with a device step counter
+    // (not with per-launch profiling; checkpoints must fall on replay edges)
+    const int K = m->opt.graph_steps;
+    if (K > 0 && !prof && nt >= K && (ckpt == 0 || ckpt % K == 0)) {
+        if ((st = ensure(m, m->stepdev, 256)) != EMM_OK) return st;
+        int *stepd = (int *)m->stepdev.p;
+        HIP_OK(m, hipMemsetAsync(stepd, 0, sizeof(int), stream));
+        emm::StepParams Pe = A.Pe, Ph = A.Ph;
+        Pe.step_base = Ph.step_base = stepd;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_OK(m, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < K; ++j) {
+            emm::launch_e_step(r, Pe, j, stream);
+            emm::launch_h_step(r, Ph, j, stream);
+        }
+        emm::launch_advance(stepd, K, stream);
+        HIP_OK(m, hipStreamEndCapture(stream, &graph));
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(m, EMM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        const int reps = nt / K;
+        for (int q = 0; q < reps; ++q) {
+            const int n = q * K;
+            if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, n / ckpt, true, stream)) != EMM_OK) return st;
+            HIP_OK(m, hipGraphLaunch(exec, stream));
+        }
+        HIP_OK(m, hipStreamSynchronize(stream));
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        n_begin = reps * K;
+    }
+    for (int n = n_begin; n < nt; ++n) {
+        if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, n / ckpt, true, stream)) != EMM_OK) return st;
         const int slot = n % ring_pairs;
         if (prof) {
             if (n >= ring_pairs && (st = harvest(slot)) != EMM_OK) return st;
             HIP_OK(m, hipEventRecord(m->ring[4 * slot + 0], stream));
         }
-        emm::launch_e_step(r, Pe, n, stream);
+        emm::launch_e_step(r, A.Pe, n, stream);
         if (prof) {
             HIP_OK(m, hipEventRecord(m->ring[4 * slot + 1], stream));
             HIP_OK(m, hipEventRecord(m->ring[4 * slot + 2], stream));
         }
-        emm::launch_h_step(r, Ph, n, stream);
+        emm::launch_h_step(r, A.Ph, n, stream);
         if (prof) HIP_OK(m, hipEventRecord(m->ring[4 * slot + 3], stream));
     }
     HIP_OK(m, hipGetLastError());
@@ -638,41 +790,447 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     if (prof)
         for (int n = std::max(0, nt - ring_pairs); n < nt; ++n)
             if ((st = harvest(n % ring_pairs)) != EMM_OK) return st;
-
-    // accumulators back, then Green's functions (Section 2.2):
-    // G^EE = (omega/omega') E'/J',  G^HE = H'/J',  J' = moment * S_f
-    std::vector<double> acc_h((size_t)nslot * nfreq * (acc_elem / sizeof(double)));
-    HIP_OK(m, hipMemcpyAsync(acc_h.data(), m->acc.p, (size_t)nslot * nfreq * acc_elem, hipMemcpyDeviceToHost, stream));
     HIP_OK(m, hipStreamSynchronize(stream));
     float loop_ms = 0.f;
     HIP_OK(m, hipEventElapsedTime(&loop_ms, m->ev_loop[0], m->ev_loop[1]));
-    bool nonfinite = false;
-    for (int s = 0; s < nsrc; ++s)
-        for (int i = 0; i < nrec; ++i)
-            for (int c = 0; c < nch; ++c)
-                for (int f = 0; f < nfreq; ++f) {
-                    const size_t k = ((size_t)(s * nrec + i) * nch + c) * nfreq + f;
-                    std::complex<double> a;
-                    if (m->opt.dft_mode == 0) {
-                        a = {acc_h[2 * k], acc_h[2 * k + 1]};
-                    } else {
-                        const float *q = reinterpret_cast<const float *>(acc_h.data()) + 4 * k;
-                        a = {(double)q[0] - (double)q[1], (double)q[2] - (double)q[3]};
-                    }
-                    std::complex<double> G = a / (sscale[s] * src[s].moment * Shat[f]);
-                    if (chans[c] < 3) G *= (2.0 * kPi * freq_hz[f]) / wp[f];
-                    if (!std::isfinite(G.real()) || !std::isfinite(G.imag())) nonfinite = true;
-                    green[2 * k] = G.real();
-                    green[2 * k + 1] = G.imag();
-                }
+    A.ckpt = ckpt;
     m->info.nt = nt;
     m->info.forward_ms = loop_ms;
-    m->info.tile_kz = P.kz;
+    m->info.tile_kz = A.Pe.kz;
     m->info.e_kernel_ms = prof ? ems : 0.0;
     m->info.h_kernel_ms = prof ? hms : 0.0;
     m->info.e_launches = prof ? nt : 0;
     m->info.h_launches = prof ? nt : 0;
+    return EMM_OK;
+}
+
+// Accumulators back to the host (complex, per slot and frequency).
+emm_status read_acc(emm_model *m, hipStream_t stream, std::vector<std::complex<double>> &acc) {
+    const Acq &A = m->acq;
+    const size_t n = (size_t)A.nsrc * A.nrec * A.nch * A.nf;
+    const size_t acc_elem = m->opt.dft_mode ? sizeof(float4) : sizeof(double2);
+    std::vector<double> raw(n * (acc_elem / sizeof(double)));
+    HIP_OK(m, hipMemcpyAsync(raw.data(), m->acc.p, n * acc_elem, hipMemcpyDeviceToHost, stream));
+    HIP_OK(m, hipStreamSynchronize(stream));
+    acc.resize(n);
+    for (size_t k = 0; k < n; ++k) {
+        if (m->opt.dft_mode == 0) {
+            acc[k] = {raw[2 * k], raw[2 * k + 1]};
+        } else {
+            const float *q = reinterpret_cast<const float *>(raw.data()) + 4 * k;
+            acc[k] = {(double)q[0] - (double)q[1], (double)q[2] - (double)q[3]};
+        }
+    }
+    return EMM_OK;
+}
+
+// d G / d acc for slot k: G = c * acc with c = (omega/omega' for E channels) / (scale moment S_f)
+std::complex<double> green_factor(const emm_model *m, size_t k) {
+    const Acq &A = m->acq;
+    const int f = (int)(k % A.nf);
+    const int c = (int)((k / A.nf) % A.nch);
+    const int s = (int)(k / ((size_t)A.nf * A.nch * A.nrec));
+    std::complex<double> g = 1.0 / (A.sscale[s] * A.src[s].moment * A.Shat[f]);
+    if (A.chans[c] < 3) g *= (2.0 * kPi * A.freqs[f]) / A.wp[f];
+    return g;
+}
+
+// Autotuner of the z chunk per thread block (tile_kz = -1): time a few
+// steps of both stencil kernels for each candidate on this model and
+// acquisition, keep the fastest (cached per source count).  The state it
+// leaves behind is discarded: the time loop starts from zero fields.
+emm_status autotune(emm_model *m, hipStream_t stream) {
+    Acq &A = m->acq;
+    if (m->opt.tile_kz >= 0 || m->tuned_kz.count(A.nsrc)) return EMM_OK;
+    const int nzv = m->np[2] - 2 * m->r;
+    std::vector<int> cand = {4, 6, 8, 12, 16, 24, 32, 48, 64, A.Pe.kz};
+    hipEvent_t e0, e1;
+    HIP_OK(m, hipEventCreate(&e0));
+    HIP_OK(m, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_kz = A.Pe.kz;
+    const int steps = 8;
+    for (int kz : cand) {
+        if (kz > nzv) continue;
+        emm::StepParams Pe = A.Pe, Ph = A.Ph;
+        Pe.kz = Ph.kz = kz;
+        Pe.zc = Ph.zc = (nzv + kz - 1) / kz;
+        Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
+        for (int n = 0; n < 2; ++n) {              // warm-up
+            emm::launch_e_step(m->r, Pe, n, stream);
+            emm::launch_h_step(m->r, Ph, n, stream);
+        }
+        HIP_OK(m, hipEventRecord(e0, stream));
+        for (int n = 0; n < steps; ++n) {
+            emm::launch_e_step(m->r, Pe, n, stream);
+            emm::launch_h_step(m->r, Ph, n, stream);
+        }
+        HIP_OK(m, hipEventRecord(e1, stream));
+        HIP_OK(m, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_OK(m, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_kz = kz;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_OK(m, hipGetLastError());
+    m->tuned_kz[A.nsrc] = best_kz;
+    for (emm::StepParams *P : {&A.Pe, &A.Ph}) {
+        P->kz = best_kz;
+        P->zc = (nzv + best_kz - 1) / best_kz;
+        P->nstencil = P->xt * P->yt * P->zc * A.nsrc;
+    }
+    return EMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_receiver *rec,
+                       int nrec, unsigned chan_mask, const double *freq_hz, int nfreq,
+                       double *green, void *hip_stream) {
+    if (!m) return fail(nullptr, EMM_ERR_ARG, "NULL model");
+    m->err.clear();
+    if (!green) return fail(m, EMM_ERR_ARG, "NULL output pointer");
+    emm_status st;
+    hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
+    if ((st = prepare(m, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq, stream)) != EMM_OK) return st;
+    if ((st = autotune(m, stream)) != EMM_OK) return st;
+    if ((st = time_loop(m, stream, m->opt.checkpoint_every)) != EMM_OK) return st;
+    std::vector<std::complex<double>> acc;
+    if ((st = read_acc(m, stream, acc)) != EMM_OK) return st;
+    bool nonfinite = false;
+    for (size_t k = 0; k < acc.size(); ++k) {
+        const std::complex<double> G = acc[k] * green_factor(m, k);
+        if (!std::isfinite(G.real()) || !std::isfinite(G.imag())) nonfinite = true;
+        green[2 * k] = G.real();
+        green[2 * k + 1] = G.imag();
+    }
     if (nonfinite) return fail(m, EMM_ERR_NONFINITE, "a DTFT accumulator is not finite (unstable run?)");
+    return EMM_OK;
+}
+
+emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm_receiver *rec,
+                        int nrec, unsigned chan_mask, const double *freq_hz, int nfreq,
+                        const double *g_obs, const double *g_bar, double *green, double *misfit,
+                        double *grad, void *hip_stream) {
+    if (!m) return fail(nullptr, EMM_ERR_ARG, "NULL model");
+    m->err.clear();
+    if (!grad || (g_obs == nullptr) == (g_bar == nullptr))
+        return fail(m, EMM_ERR_ARG, "need grad and exactly one of g_obs, g_bar");
+    emm_status st;
+    hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
+    const int ck = m->opt.checkpoint_every > 0 ? m->opt.checkpoint_every : 50;
+    // forward with checkpoints, unless the last forward stored them for the same acquisition
+    if (!(m->acq.ckpt > 0 && same_acquisition(m->acq, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq))) {
+        if ((st = prepare(m, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq, stream)) != EMM_OK) return st;
+        if ((st = autotune(m, stream)) != EMM_OK) return st;
+        if ((st = time_loop(m, stream, ck)) != EMM_OK) return st;
+    }
+    const Acq &A = m->acq;
+    const int ckpt = A.ckpt;
+    std::vector<std::complex<double>> acc;
+    if ((st = read_acc(m, stream, acc)) != EMM_OK) return st;
+    const size_t nd = acc.size();
+    // adjoint-source coefficients per slot: dL/du_n = sum_f Re(Acoef_f z_f^n) with
+    // Acoef = conj(gbar) dG/dacc, gbar = dL/dRe G + i dL/dIm G; for the log misfit
+    // L = 1/2 sum |log(G/G_obs)|^2, gbar = r / conj(G), r = log(G/G_obs).
+    std::vector<double2> Acoef(nd);
+    double chi = 0.0;
+    bool nonfinite = false;
+    for (size_t k = 0; k < nd; ++k) {
+        const std::complex<double> c = green_factor(m, k);
+        const std::complex<double> G = acc[k] * c;
+        if (!std::isfinite(G.real()) || !std::isfinite(G.imag())) nonfinite = true;
+        if (green) {
+            green[2 * k] = G.real();
+            green[2 * k + 1] = G.imag();
+        }
+        std::complex<double> gb;
+        if (g_obs) {
+            const std::complex<double> Go(g_obs[2 * k], g_obs[2 * k + 1]);
+            const std::complex<double> rr = std::log(G / Go);
+            chi += 0.5 * std::norm(rr);
+            gb = rr / std::conj(G);
+        } else {
+            gb = {g_bar[2 * k], g_bar[2 * k + 1]};
+        }
+        const std::complex<double> a = std::conj(gb) * c;
+        Acoef[k] = make_double2(a.real(), a.imag());
+    }
+    if (nonfinite) return fail(m, EMM_ERR_NONFINITE, "a DTFT accumulator is not finite (unstable run?)");
+    if (misfit) *misfit = g_obs ? chi : 0.0;
+
+    // ---- adjoint set-up ----
+    const int r = m->r, L = 2 * r, nb = m->nb, nt = A.nt;
+    const int n1 = m->np[0], n2 = m->np[1], n3 = m->np[2];
+    const long long fstride = A.Pe.fstride, plane = A.Pe.plane;
+    // transposed FD tables: (D-)^T has the D+ shape, (D+)^T the D- shape
+    if (!m->tabT.p) {
+        std::vector<float> t;
+        std::vector<size_t> off;
+        for (int kind = 0; kind < 2; ++kind)          // 0: transposed D-, 1: transposed D+
+            for (int a = 0; a < 3; ++a) {
+                const std::vector<double> &c = kind == 0 ? m->cm[a] : m->cp[a];
+                const int n = m->np[a];
+                off.push_back(t.size());
+                for (int q = 0; q < n; ++q)
+                    for (int mm = 0; mm < L; ++mm) {
+                        // row q of the transpose: source row q - r + 1 + mm (D-) or q - r + mm (D+)
+                        const int row = kind == 0 ? q - r + 1 + mm : q - r + mm;
+                        t.push_back(row >= r && row <= n - 1 - r ? (float)c[(size_t)row * L + (L - 1 - mm)] : 0.f);
+                    }
+            }
+        if ((st = ensure(m, m->tabT, t.size() * sizeof(float))) != EMM_OK) return st;
+        HIP_OK(m, hipMemcpy(m->tabT.p, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    const float *tT = (const float *)m->tabT.p;
+    const float *cmT[3] = {tT, tT + (size_t)n1 * L, tT + (size_t)(n1 + n2) * L};
+    const float *cpT[3] = {tT + (size_t)(n1 + n2 + n3) * L, tT + (size_t)(2 * n1 + n2 + n3) * L,
+                           tT + (size_t)(2 * n1 + 2 * n2 + n3) * L};
+    // CPML tables concatenated per kind [x | y | z]
+    {
+        std::vector<float> c;
+        // fetch the per-axis tables of this forward back from the device buffer
+        std::vector<float> all((n1 + n2 + n3) * 4);
+        HIP_OK(m, hipMemcpy(all.data(), m->cpml.p, all.size() * sizeof(float), hipMemcpyDeviceToHost));
+        // device layout: axis a: a_int, b_int, a_half, b_half (each n_a)
+        size_t o = 0;
+        const int nn[3] = {n1, n2, n3};
+        size_t base[3];
+        for (int a = 0; a < 3; ++a) {
+            base[a] = o;
+            o += 4 * (size_t)nn[a];
+        }
+        for (int kind = 0; kind < 4; ++kind)
+            for (int a = 0; a < 3; ++a)
+                for (int i = 0; i < nn[a]; ++i) c.push_back(all[base[a] + (size_t)kind * nn[a] + i]);
+        if ((st = ensure(m, m->adjcpml, c.size() * sizeof(float))) != EMM_OK) return st;
+        HIP_OK(m, hipMemcpy(m->adjcpml.p, c.data(), c.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    const float *acp = (const float *)m->adjcpml.p;
+    const size_t nsum = (size_t)n1 + n2 + n3;
+    // slab arrays per source: x [n3][n2][2nb], y [n3][2nb][pitch], z [2nb][n2][pitch]
+    const long long sxs = nb ? (long long)n3 * n2 * 2 * nb : 0;
+    const long long sys = nb ? (long long)n3 * 2 * nb * m->pitch : 0;
+    const long long szs = nb ? (long long)2 * nb * plane : 0;
+    const long long slab_src = 2 * (sxs + sys + szs);          // 6 arrays
+    if ((st = ensure(m, m->adjf, (size_t)6 * nsrc * fstride * sizeof(float))) != EMM_OK) return st;
+    if ((st = ensure(m, m->adjq, (size_t)std::max<long long>(1, 2 * nsrc * slab_src) * sizeof(float))) != EMM_OK) return st;
+    if ((st = ensure(m, m->adjt, (size_t)std::max<long long>(1, nsrc * slab_src) * sizeof(float))) != EMM_OK) return st;
+    if ((st = ensure(m, m->snaps, (size_t)(ckpt + 1) * 3 * nsrc * fstride * sizeof(float))) != EMM_OK) return st;
+    if ((st = ensure(m, m->grad, (size_t)3 * nsrc * fstride * sizeof(double))) != EMM_OK) return st;
+    HIP_OK(m, hipMemsetAsync(m->adjf.p, 0, (size_t)6 * nsrc * fstride * sizeof(float), stream));
+    if (nb) HIP_OK(m, hipMemsetAsync(m->adjq.p, 0, (size_t)2 * nsrc * slab_src * sizeof(float), stream));
+    HIP_OK(m, hipMemsetAsync(m->grad.p, 0, (size_t)3 * nsrc * fstride * sizeof(double), stream));
+
+    // receiver injection lists (CSR over target cells, fixed order): E channels
+    // target Et (scaled by dt/eps), H channels target Hb
+    std::vector<int> rowE, rowH, itE, itH, compE, compH;
+    std::vector<float> wE, wH;
+    std::vector<long long> cellE, cellH, mcE, mcH;
+    for (int kind = 0; kind < 2; ++kind) {            // 0: E channels (items_hstep), 1: H channels
+        const std::vector<int> &items = kind == 0 ? A.items_hstep : A.items_estep;
+        const std::vector<float> &wts = kind == 0 ? A.w_hstep : A.w_estep;
+        std::vector<std::pair<long long, std::pair<int, float>>> ent;  // (target key, (slot, weight))
+        const int nit = (int)items.size() / 6;
+        for (int q = 0; q < nit; ++q) {
+            const int *inf = &items[6 * q];
+            const int s = inf[0], f = inf[1], bx = inf[2], by = inf[3], bz = inf[4], slot = inf[5];
+            const float *w = &wts[(size_t)3 * L * q];
+            for (int c3 = 0; c3 < L; ++c3)
+                for (int b = 0; b < L; ++b)
+                    for (int a = 0; a < L; ++a) {
+                        const long long mc = (long long)(bz + c3) * plane + (long long)(by + b) * m->pitch + bx + a;
+                        const long long key = ((long long)f * nsrc + s) * fstride + mc;
+                        ent.push_back({key, {slot, w[a] * w[L + b] * w[2 * L + c3]}});
+                    }
+        }
+        std::stable_sort(ent.begin(), ent.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        std::vector<int> &row = kind == 0 ? rowE : rowH;
+        std::vector<int> &it = kind == 0 ? itE : itH;
+        std::vector<int> &cp_ = kind == 0 ? compE : compH;
+        std::vector<float> &ww = kind == 0 ? wE : wH;
+        std::vector<long long> &cell = kind == 0 ? cellE : cellH;
+        std::vector<long long> &mcell = kind == 0 ? mcE : mcH;
+        for (size_t e = 0; e < ent.size(); ++e) {
+            if (e == 0 || ent[e].first != ent[e - 1].first) {
+                row.push_back((int)it.size());
+                const long long key = ent[e].first;
+                const int f = (int)(key / ((long long)nsrc * fstride));
+                cp_.push_back(f);
+                cell.push_back(key - (long long)f * nsrc * fstride);    // within the component array
+                mcell.push_back(key % fstride);
+            }
+            it.push_back(ent[e].second.first);
+            ww.push_back(ent[e].second.second);
+        }
+        row.push_back((int)it.size());
+    }
+    // one device buffer for both lists
+    auto bytes_of = [](const auto &v) { return v.size() * sizeof(v[0]); };
+    const size_t inj_bytes = bytes_of(rowE) + bytes_of(rowH) + bytes_of(itE) + bytes_of(itH) + bytes_of(wE) +
+                             bytes_of(wH) + bytes_of(cellE) + bytes_of(cellH) + bytes_of(mcE) + bytes_of(mcH) +
+                             bytes_of(compE) + bytes_of(compH) + 16 * 12;
+    if ((st = ensure(m, m->inj, inj_bytes)) != EMM_OK) return st;
+    if ((st = ensure(m, m->injA, nd * sizeof(double2))) != EMM_OK) return st;
+    HIP_OK(m, hipMemcpy(m->injA.p, Acoef.data(), nd * sizeof(double2), hipMemcpyHostToDevice));
+    char *ip = (char *)m->inj.p;
+    size_t io = 0;
+    auto up = [&](const auto &v) -> const void * {
+        io = (io + 15) / 16 * 16;
+        void *d = ip + io;
+        if (!v.empty()) (void)hipMemcpy(d, v.data(), bytes_of(v), hipMemcpyHostToDevice);
+        io += bytes_of(v);
+        return d;
+    };
+    float *AF = (float *)m->adjf.p;
+    float *Et[3] = {AF, AF + (size_t)nsrc * fstride, AF + (size_t)2 * nsrc * fstride};
+    float *Hb[3] = {AF + (size_t)3 * nsrc * fstride, AF + (size_t)4 * nsrc * fstride, AF + (size_t)5 * nsrc * fstride};
+    emm::InjectParams IE{}, IH{};
+    IE.ncells = (int)cellE.size();
+    IE.nf = A.nf;
+    IE.row = (const int *)up(rowE);
+    IE.item = (const int *)up(itE);
+    IE.w = (const float *)up(wE);
+    IE.cell = (const long long *)up(cellE);
+    IE.mcell = (const long long *)up(mcE);
+    IE.comp = (const int *)up(compE);
+    IE.A = (const double2 *)m->injA.p;
+    IE.phase = A.Ph.phase;                    // E stamps (n + 1) dt
+    IE.F1 = Et[0];
+    IE.F2 = Et[1];
+    IE.F3 = Et[2];
+    IE.ce1 = m->ce[0];
+    IE.ce2 = m->ce[1];
+    IE.ce3 = m->ce[2];
+    IE.scale_ce = 1;
+    IH = IE;
+    IH.ncells = (int)cellH.size();
+    IH.row = (const int *)up(rowH);
+    IH.item = (const int *)up(itH);
+    IH.w = (const float *)up(wH);
+    IH.cell = (const long long *)up(cellH);
+    IH.mcell = (const long long *)up(mcH);
+    IH.comp = (const int *)up(compH);
+    IH.phase = A.Pe.phase;                    // H stamps (n + 1/2) dt
+    IH.F1 = Hb[0];
+    IH.F2 = Hb[1];
+    IH.F3 = Hb[2];
+    IH.scale_ce = 0;
+
+    // adjoint gather parameters
+    float *AQ = (float *)m->adjq.p, *AT_ = (float *)m->adjt.p;
+    auto slab_ptrs = [&](float *base, float **out) {
+        // [x0 x1 | y0 y1 | z0 z1], each nsrc * stride
+        out[0] = base;
+        out[1] = base + nsrc * sxs;
+        out[2] = base + 2 * nsrc * sxs;
+        out[3] = base + 2 * nsrc * sxs + nsrc * sys;
+        out[4] = base + 2 * nsrc * sxs + 2 * nsrc * sys;
+        out[5] = base + 2 * nsrc * sxs + 2 * nsrc * sys + nsrc * szs;
+    };
+    emm::AdjParams PE{}, PH{};               // PE: reverse of the H update (-> Et), PH: of the E update (-> Hb)
+    PE.n1 = n1;
+    PE.n2 = n2;
+    PE.n3 = n3;
+    PE.pitch = m->pitch;
+    PE.r = r;
+    PE.nb = nb;
+    PE.nsrc = nsrc;
+    PE.fstride = fstride;
+    PE.ce1 = m->ce[0];
+    PE.ce2 = m->ce[1];
+    PE.ce3 = m->ce[2];
+    PE.a_int = acp;
+    PE.b_int = acp + nsum;
+    PE.a_half = acp + 2 * nsum;
+    PE.b_half = acp + 3 * nsum;
+    PE.sxs = sxs;
+    PE.sys = sys;
+    PE.szs = szs;
+    PE.gstride = fstride;
+    PE.grad = (double *)m->grad.p;
+    PH = PE;
+    PE.in1 = Hb[0];
+    PE.in2 = Hb[1];
+    PE.in3 = Hb[2];
+    PE.out1 = Et[0];
+    PE.out2 = Et[1];
+    PE.out3 = Et[2];
+    PE.scale = (float)(m->dt / kMu0);
+    PE.tx = cpT[0];
+    PE.ty = cpT[1];
+    PE.tz = cpT[2];
+    slab_ptrs(AQ, PE.Q);
+    slab_ptrs(AT_, PE.T);
+    PH.in1 = Et[0];
+    PH.in2 = Et[1];
+    PH.in3 = Et[2];
+    PH.out1 = Hb[0];
+    PH.out2 = Hb[1];
+    PH.out3 = Hb[2];
+    PH.scale = 1.0f;
+    PH.tx = cmT[0];
+    PH.ty = cmT[1];
+    PH.tz = cmT[2];
+    slab_ptrs(AQ + nsrc * slab_src, PH.Q);
+    slab_ptrs(AT_, PH.T);
+
+    // forward recompute parameters: no receiver DTFT
+    emm::StepParams Pe = A.Pe, Ph = A.Ph;
+    Pe.nrecblk = Ph.nrecblk = 0;
+    Pe.nitems = Ph.nitems = 0;
+    float *snap = (float *)m->snaps.p;
+    const size_t snap_bytes = (size_t)3 * nsrc * fstride * sizeof(float);
+    const int nseg = (nt + ckpt - 1) / ckpt;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int n0 = sgi * ckpt, nend = std::min(n0 + ckpt, nt);
+        if ((st = copy_state(m, sgi, false, stream)) != EMM_OK) return st;
+        HIP_OK(m, hipMemcpyAsync(snap, m->fields.p, snap_bytes, hipMemcpyDeviceToDevice, stream));
+        for (int n = n0; n < nend; ++n) {
+            emm::launch_e_step(r, Pe, n, stream);
+            emm::launch_h_step(r, Ph, n, stream);
+            HIP_OK(m, hipMemcpyAsync(snap + (size_t)(n - n0 + 1) * 3 * nsrc * fstride, m->fields.p, snap_bytes,
+                                     hipMemcpyDeviceToDevice, stream));
+        }
+        for (int n = nend - 1; n >= n0; --n) {
+            if (nb) emm::launch_adj_filter(true, PE, stream);
+            emm::launch_adj_gather(r, true, PE, stream);
+            emm::launch_adj_inject(IE, n, stream);
+            PH.E_next = snap + (size_t)(n - n0 + 1) * 3 * nsrc * fstride;
+            PH.E_prev = snap + (size_t)(n - n0) * 3 * nsrc * fstride;
+            if (nb) emm::launch_adj_filter(false, PH, stream);
+            emm::launch_adj_gather(r, false, PH, stream);
+            emm::launch_adj_inject(IH, n, stream);
+        }
+        HIP_OK(m, hipGetLastError());
+    }
+    // sum over sources, drop the pitch padding, fold the model padding back onto
+    // the input cells, and change sign: d/d log sigma = -d/d log(dt/eps)
+    std::vector<double> g((size_t)3 * nsrc * fstride);
+    HIP_OK(m, hipMemcpyAsync(g.data(), m->grad.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_OK(m, hipStreamSynchronize(stream));
+    const int nd0 = m->n[0], nd1 = m->n[1], nd2 = m->n[2];
+    std::fill(grad, grad + (size_t)3 * nd0 * nd1 * nd2, 0.0);
+    for (int c = 0; c < 3; ++c)
+        for (int s = 0; s < nsrc; ++s)
+            for (int k = r; k <= n3 - 1 - r; ++k) {
+                const int kk = std::min(std::max(k - m->nbe, 0), nd2 - 1);
+                for (int j = r; j <= n2 - 1 - r; ++j) {
+                    const int jj = std::min(std::max(j - m->nbe, 0), nd1 - 1);
+                    const double *row = &g[((size_t)s * 3 + c) * fstride + (size_t)k * plane + (size_t)j * m->pitch];
+                    double *out = grad + (((size_t)c * nd2 + kk) * nd1 + jj) * nd0;
+                    for (int i = r; i <= n1 - 1 - r; ++i) {
+                        const int ii = std::min(std::max(i - m->nbe, 0), nd0 - 1);
+                        out[ii] -= row[i];
+                    }
+                }
+            }
     return EMM_OK;
 }
 

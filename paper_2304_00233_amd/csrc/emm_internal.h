@@ -49,9 +49,12 @@ struct StepParams {
     double2 *acc;                    // [slots][nf]           (dft_mode 0)
     float4 *acck;                    // [slots][nf] re,cre,im,cim (dft_mode 1)
     int dft_mode;
+    // step index = *step_base + n when step_base is set (graph replays), else n
+    const int *step_base;
 };
 
 void launch_e_step(int r, const StepParams &p, int n, hipStream_t s);
+void launch_advance(int *step, int k, hipStream_t s);
 void launch_h_step(int r, const StepParams &p, int n, hipStream_t s);
 int block_threads();
 

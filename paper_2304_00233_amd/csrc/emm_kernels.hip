@@ -96,7 +96,8 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
 // buffer is rewritten only after every wave has passed the barrier that
 // follows its last use.
 template <int R, bool HS>
-__global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n) {
+__global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg) {
+    const int n = (p.step_base ? *p.step_base : 0) + n_arg;
     constexpr int L = 2 * R;
     constexpr int HL = HS ? R - 1 : R;        // halo below the own index
     constexpr int W = kTileX + L - 1;         // LDS row length incl. halo
@@ -116,13 +117,16 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n) {
         rec_dft<R>(p, blk, A1, A2, A3, n);
         return;
     }
+    // logical tile: source fastest, then x, y, z chunk, so the blocks of all
+    // sources for one spatial tile run together (on one XCD) and share the
+    // model and table reads through L2
     int t = xcd_tile(blk - p.nrecblk, p.nstencil);
+    const int s = t % p.nsrc;
+    t /= p.nsrc;
     const int bxt = t % p.xt;
     t /= p.xt;
     const int byt = t % p.yt;
-    t /= p.yt;
-    const int bzt = t % p.zc;
-    const int s = t / p.zc;
+    const int bzt = t / p.yt;
 
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const int i0 = bxt * kTileX, j0 = R + byt * TY;
@@ -350,6 +354,15 @@ static void launch(int r, const StepParams &p, int n, hipStream_t s) {
 }
 
 void launch_e_step(int r, const StepParams &p, int n, hipStream_t s) { launch<false>(r, p, n, s); }
+
+// graph replays: advance the device step counter by k after each replay
+__global__ void advance_kernel(int *step, int k) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) step[0] += k;
+}
+
+void launch_advance(int *step, int k, hipStream_t s) {
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, step, k);
+}
 void launch_h_step(int r, const StepParams &p, int n, hipStream_t s) { launch<true>(r, p, n, s); }
 
 }  // namespace emm

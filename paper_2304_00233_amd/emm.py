@@ -24,7 +24,7 @@ STATUS = {0: "EMM_OK", -1: "EMM_ERR_ARG", -2: "EMM_ERR_GRID", -3: "EMM_ERR_MODEL
           -4: "EMM_ERR_GEOMETRY", -5: "EMM_ERR_FREQ", -6: "EMM_ERR_CFL",
           -7: "EMM_ERR_NONFINITE", -8: "EMM_ERR_OOM", -9: "EMM_ERR_DEVICE"}
 EXPORTED = ("emm_default_options", "emm_create", "emm_query", "emm_forward",
-            "emm_destroy", "emm_status_str", "emm_last_error")
+            "emm_gradient", "emm_destroy", "emm_status_str", "emm_last_error")
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -42,7 +42,8 @@ class emm_options(C.Structure):
                 ("nt", C.c_int), ("dft_mode", C.c_int),
                 ("cpml_R", C.c_double), ("cpml_npow", C.c_double),
                 ("cpml_alpha_max", C.c_double), ("wavelet_fpeak", C.c_double),
-                ("allow_unstable", C.c_int), ("profile", C.c_int), ("tile_kz", C.c_int)]
+                ("allow_unstable", C.c_int), ("profile", C.c_int), ("tile_kz", C.c_int),
+                ("checkpoint_every", C.c_int), ("graph_steps", C.c_int)]
 
 
 class emm_source(C.Structure):
@@ -82,6 +83,10 @@ def _load():
                                 C.POINTER(emm_receiver), C.c_int, C.c_uint, _dp, C.c_int,
                                 _dp, C.c_void_p]
     lib.emm_forward.restype = C.c_int
+    lib.emm_gradient.argtypes = [C.c_void_p, C.POINTER(emm_source), C.c_int,
+                                 C.POINTER(emm_receiver), C.c_int, C.c_uint, _dp, C.c_int,
+                                 _dp, _dp, _dp, _dp, _dp, C.c_void_p]
+    lib.emm_gradient.restype = C.c_int
     lib.emm_destroy.argtypes = [C.c_void_p]
     lib.emm_destroy.restype = None
     lib.emm_status_str.argtypes = [C.c_int]
@@ -163,6 +168,49 @@ def emm_forward(model, sources, receivers, chan_mask: int, freqs, src_comp=None,
     return g.reshape(ns, nr, nch, nf)
 
 
+def _acq(sources, receivers, freqs, src_comp, moments):
+    sources = np.atleast_2d(np.asarray(sources, dtype=np.float64))
+    receivers = np.atleast_2d(np.asarray(receivers, dtype=np.float64))
+    freqs = np.ascontiguousarray(freqs, dtype=np.float64)
+    ns, nr = len(sources), len(receivers)
+    comp = np.zeros(ns, dtype=np.int32) if src_comp is None else np.asarray(src_comp)
+    mom = np.ones(ns) if moments is None else np.asarray(moments, dtype=np.float64)
+    S = (emm_source * max(ns, 1))(*[emm_source(*sources[i], int(comp[i]), float(mom[i]))
+                                    for i in range(ns)])
+    R = (emm_receiver * max(nr, 1))(*[emm_receiver(*receivers[i]) for i in range(nr)])
+    return S, ns, R, nr, freqs
+
+
+def emm_gradient(model, shape, sources, receivers, chan_mask: int, freqs, g_obs=None,
+                 g_bar=None, src_comp=None, moments=None, stream=None):
+    """Discrete-adjoint gradient (see emm.h).  shape = (n1, n2, n3) of the
+    model; g_obs or g_bar complex [nsrc][nrec][nchan][nfreq].  Returns
+    (grad[3][n3][n2][n1] = dL/d log sigma, G, misfit)."""
+    S, ns, R, nr, freqs = _acq(sources, receivers, freqs, src_comp, moments)
+    nf = len(freqs)
+    nch = bin(chan_mask & 0x3F).count("1")
+    n1, n2, n3 = shape
+
+    def pack(z):
+        if z is None:
+            return None
+        z = np.asarray(z, dtype=np.complex128).reshape(-1)
+        out = np.empty(2 * z.size)
+        out[0::2], out[1::2] = z.real, z.imag
+        return out
+    go, gb = pack(g_obs), pack(g_bar)
+    green = np.zeros(2 * ns * nr * nch * nf)
+    grad = np.zeros(3 * n1 * n2 * n3)
+    mis = C.c_double(0.0)
+    _check(_lib.emm_gradient(model, S, ns, R, nr, C.c_uint(chan_mask), freqs.ctypes.data_as(_dp),
+                             nf, go.ctypes.data_as(_dp) if go is not None else None,
+                             gb.ctypes.data_as(_dp) if gb is not None else None,
+                             green.ctypes.data_as(_dp), C.byref(mis), grad.ctypes.data_as(_dp),
+                             stream), model)
+    G = (green[0::2] + 1j * green[1::2]).reshape(ns, nr, nch, nf)
+    return grad.reshape(3, n3, n2, n1), G, mis.value
+
+
 def emm_destroy(model) -> None:
     _lib.emm_destroy(model)
 
@@ -194,6 +242,16 @@ class Model:
                            w.freqs if freqs is None else freqs,
                            w.src_comp if src_comp is None and sources is None else src_comp,
                            stream=stream)
+
+    def gradient(self, g_obs=None, g_bar=None, sources=None, receivers=None, freqs=None,
+                 chan_mask=None, src_comp=None, stream=None):
+        w = self.w
+        return emm_gradient(self.h, w.shape, w.sources if sources is None else sources,
+                            w.receivers if receivers is None else receivers,
+                            w.chan_mask if chan_mask is None else chan_mask,
+                            w.freqs if freqs is None else freqs, g_obs=g_obs, g_bar=g_bar,
+                            src_comp=w.src_comp if src_comp is None and sources is None else src_comp,
+                            stream=stream)
 
     def info(self) -> dict:
         return emm_query(self.h).as_dict()

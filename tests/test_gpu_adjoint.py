@@ -1,0 +1,99 @@
+"""GPU discrete adjoint (emm_gradient) against the FP64 oracle's adjoint,
+which is itself pinned by central differences (tests/test_oracle_adjoint.py).
+
+The misfit is chi = 1/2 sum |log(G/G_obs)|^2 over E and H data; G_obs comes
+from a perturbed model.  The GPU runs FP32 fields with FP64 DTFT
+accumulators and FP64 gradient accumulators; the bar is a relative L2 error
+of the whole gradient field and a per-cell check on the cells that carry the
+gradient (above 1 % of its largest magnitude).  Also: bitwise determinism
+across checkpoint intervals and reuse of a forward's checkpoints, and the
+cotangent (g_bar) entry equals the misfit entry for the same cotangent.
+"""
+import numpy as np
+import pytest
+
+from oracle import forward as F
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+L2_TOL = 2e-3
+CELL_TOL = 1e-2
+
+
+@pytest.fixture(scope="module")
+def emm():
+    from paper_2304_00233_amd import emm as E
+    return E
+
+
+def _case(seed=31, nsrc=1, shape=(21, 19, 17), rd=2, nb=4, nt=300):
+    w = configs.small_case(seed=seed, shape=shape, rd=rd, nb=nb, ne=rd + 1, nt=nt, nrec=5,
+                           nsrc=nsrc, freqs=(0.5, 1.5), nu_axes=(False, True, True))
+    s = np.float32(1.3)
+    wo = w.with_(rho11=w.rho11 * s, rho22=w.rho22 * s, rho33=w.rho33 * s)
+    return w, wo
+
+
+def _compare(g_gpu, g_ora, label):
+    l2 = np.linalg.norm(g_gpu - g_ora) / np.linalg.norm(g_ora)
+    big = np.abs(g_ora) >= 1e-2 * np.max(np.abs(g_ora))
+    cell = np.max(np.abs(g_gpu[big] - g_ora[big]) / np.abs(g_ora[big]))
+    print(f"[adjoint] {label}: rel L2 {l2:.2e}, worst cell above 1% {cell:.2e} "
+          f"({big.sum()} cells)", flush=True)
+    assert l2 <= L2_TOL and cell <= CELL_TOL, (l2, cell)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(seed=32, rd=1, shape=(18, 17, 16)),
+                                dict(seed=33, rd=4, shape=(25, 23, 21), nb=5),
+                                dict(seed=34, nsrc=2), dict(seed=35, nb=0)],
+                         ids=["r2", "r1", "r4", "two_sources", "no_cpml"])
+def test_gradient_matches_oracle_adjoint(emm, kw):
+    w, wo = _case(**kw)
+    st = F.make_setup(w, 2.0 * np.sqrt(1.5))
+    G_obs, _ = F.forward(wo, dt_override=st.dt)
+    chi_o, g_o, G_o = F.misfit_gradient(w, G_obs, frozen=st)
+    with emm.Model(w) as m:
+        g, G, chi = m.gradient(g_obs=G_obs)
+    assert chi == pytest.approx(chi_o, rel=1e-4)
+    _compare(g, g_o, f"{w.name}")
+
+
+def test_checkpoint_interval_and_reuse_are_bitwise(emm):
+    w, wo = _case(seed=36, nt=230)
+    G_obs, _ = F.forward(wo)
+    with emm.Model(w, checkpoint_every=17) as m:
+        m.forward()                                   # stores checkpoints
+        g1, _, c1 = m.gradient(g_obs=G_obs)           # reuses them
+        g2, _, c2 = m.gradient(g_obs=G_obs)           # and again
+    with emm.Model(w, checkpoint_every=40) as m:
+        g3, _, c3 = m.gradient(g_obs=G_obs)           # runs its own forward
+    assert np.array_equal(g1, g2) and c1 == c2
+    assert np.array_equal(g1, g3) and c1 == c3
+
+
+def test_cotangent_entry_equals_misfit_entry(emm):
+    w, wo = _case(seed=37, nt=200)
+    G_obs, _ = F.forward(wo)
+    with emm.Model(w) as m:
+        g1, G, _ = m.gradient(g_obs=G_obs)
+        gbar = np.log(G / G_obs) / np.conj(G)        # dchi/dRe G + i dchi/dIm G
+        g2, _, _ = m.gradient(g_bar=gbar)
+    assert np.allclose(g1, g2, rtol=1e-6, atol=1e-12 * np.max(np.abs(g1)))
+
+
+def test_torch_autograd_function(emm):
+    torch = pytest.importorskip("torch")
+    from paper_2304_00233_amd import autograd as AG
+    w, wo = _case(seed=38, nt=200)
+    G_obs, _ = F.forward(wo)
+    with emm.Model(w) as m:
+        dt = m.info()["dt"]
+        g_ref, _, chi_ref = m.gradient(g_obs=G_obs)
+    ls = AG.log_sigma_of(w).requires_grad_(True)
+    G = AG.green(ls, w, dt_override=dt, checkpoint_every=40)
+    r = torch.log(G / torch.from_numpy(G_obs))
+    loss = 0.5 * torch.sum(r.real ** 2 + r.imag ** 2)
+    loss.backward()
+    assert float(loss) == pytest.approx(chi_ref, rel=1e-9)
+    assert np.allclose(ls.grad.numpy(), g_ref, rtol=1e-6, atol=1e-12 * np.max(np.abs(g_ref)))
