@@ -24,10 +24,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of one E-step launch measured with rocprofv3 --pmc FETCH_SIZE
-# and WRITE_SIZE on this workload, scaled by the copy-kernel calibration;
-# None until measured for the current kernel.
-E_STEP_TRAFFIC_BYTES = None
+# HBM traffic of one E-step launch on the marine workload, measured with
+# rocprofv3 --pmc FETCH_SIZE (x 2.0) and --pmc WRITE_SIZE (x 1.0), the factors
+# from a 1 GiB copy kernel: 68 651 KiB read and 46 148 KiB written.  Valid for
+# the kernel as profiled; set to None when the kernel changes until re-measured.
+E_STEP_TRAFFIC_BYTES = (68651 * 2.0 + 46148 * 1.0) * 1024
 
 
 def log(*a):
@@ -48,13 +49,51 @@ def cpu_baseline(w, nt_sample: int):
                       f"{dt:.1f} s wall"}
 
 
+def batched_comparison(emm, w, nsrc: int, group: int, ckpt: int):
+    """16 towed x-dipoles (500 m spacing, 50 m above the seabed) on the same
+    model: the plain loop of one-source forwards, one batched forward of all
+    sources, and batched forward + gradient (log misfit against data from
+    the batched forward scaled by 1.01) in groups of `group` sources that
+    keep checkpoints every `ckpt` steps.  Returns timings and the largest
+    difference between batched and plain results."""
+    import numpy as np
+    from workloads import configs
+    src = configs.towline_sources(nsrc, 500.0, 950.0)
+    comp = np.zeros(nsrc, dtype=np.int32)
+    out = {"sources": nsrc, "gradient_group": group, "checkpoint_every": ckpt}
+    with emm.Model(w, tile_kz=-1) as m:
+        m.forward(sources=src[:1], src_comp=comp[:1])           # tune + warm
+        t = time.perf_counter()
+        plain = [m.forward(sources=src[i:i + 1], src_comp=comp[i:i + 1]) for i in range(nsrc)]
+        out["plain_forward_loop_s"] = time.perf_counter() - t
+        m.forward(sources=src, src_comp=comp)                   # tune for nsrc + warm
+        t = time.perf_counter()
+        Gb = m.forward(sources=src, src_comp=comp)
+        out["batched_forward_s"] = time.perf_counter() - t
+    Gp = np.concatenate(plain, axis=0)
+    out["max_abs_diff_batched_vs_plain"] = float(np.max(np.abs(Gb - Gp)))
+    G_obs = Gb * 1.01
+    with emm.Model(w, tile_kz=-1, checkpoint_every=ckpt) as m:
+        m.forward(sources=src[:group], src_comp=comp[:group])   # tune + warm
+        t = time.perf_counter()
+        for g0 in range(0, nsrc, group):
+            sl = slice(g0, min(nsrc, g0 + group))
+            m.forward(sources=src[sl], src_comp=comp[sl])
+            m.gradient(g_obs=G_obs[sl], sources=src[sl], src_comp=comp[sl])
+        out["batched_forward_gradient_s"] = time.perf_counter() - t
+    out["speedup_batched_forward_vs_plain_loop"] = out["plain_forward_loop_s"] / out["batched_forward_s"]
+    out["batched_fwd_grad_over_plain_forward_loop"] = (out["batched_forward_gradient_s"] /
+                                                       out["plain_forward_loop_s"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--workload", default="marine", choices=["marine", "large", "cube"],
                     help="marine: the headline 128x128x96 workload; large: the 400x400x200 "
                          "marine grid (one source); cube: uniform n^3 (--cube-n)")
@@ -63,6 +102,10 @@ def main():
     ap.add_argument("--nt", type=int, default=0, help="override the time-step count")
     ap.add_argument("--graph", type=int, default=0, help="time steps per captured hipGraph")
     ap.add_argument("--tile-kz", type=int, default=-1, help="z planes per block (-1: autotuned)")
+    ap.add_argument("--batched", type=int, default=16,
+                    help="sources of the batched comparison (0: skip)")
+    ap.add_argument("--grad-group", type=int, default=8)
+    ap.add_argument("--grad-ckpt", type=int, default=130)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -143,12 +186,16 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "e_step (curl H + CPML + J + E update + H DTFT)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": E_STEP_TRAFFIC_BYTES,
+                     "traffic": E_STEP_TRAFFIC_BYTES if args.workload == "marine" else None,
                      "bytes_per_launch": info["e_bytes"], "avg_launch_us": e_avg_s * 1e6},
         "h_step": {"bytes_per_launch": info["h_bytes"], "avg_launch_us": h_avg_s * 1e6,
                    "achieved_GBs": info["h_bytes"] / h_avg_s / 1e9},
         "device_loop_ms_per_step": dev_ms / args.steps,
     }
+    if args.batched and args.workload == "marine":
+        log(f"[bench] batched comparison with {args.batched} sources")
+        out["batched"] = batched_comparison(emm, w, args.batched, args.grad_group, args.grad_ckpt)
+        log(f"[bench] batched: {out['batched']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
