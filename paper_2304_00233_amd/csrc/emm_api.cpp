@@ -577,7 +577,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.fstride = fstride;
     P.nb = nb;
     P.xt = m->pitch / emm::kTileX;
-    P.yt = (m->np[1] - 2 * r + 3) / 4;
+    P.yt = (m->np[1] - 2 * r + emm::kTileY - 1) / emm::kTileY;
     P.kz = choose_kz(m, P.xt, P.yt, nsrc);
     P.zc = (m->np[2] - 2 * r + P.kz - 1) / P.kz;
     P.nsrc = nsrc;

@@ -10,6 +10,7 @@ namespace emm {
 
 constexpr int kTileX = 64;     // one wavefront row along x (wave64)
 constexpr int kMaxR = 4;       // 8th order in space at most
+constexpr int kTileY = 4;      // rows (wavefronts) per thread block
 
 // Everything one half-step kernel needs; passed by value.
 struct StepParams {

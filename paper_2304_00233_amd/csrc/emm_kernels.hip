@@ -24,7 +24,7 @@
 
 namespace emm {
 
-constexpr int TY = 4;
+constexpr int TY = kTileY;
 constexpr int NT = kTileX * TY;
 
 int block_threads() { return NT; }
@@ -55,7 +55,7 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
     for (int q = lane; q < L * L * L; q += 64) {
         const int a = q % L, b = (q / L) % L, c = q / (L * L);
         const float wt = w[a] * w[L + b] * w[2 * L + c];
-        u += (double)wt * (double)F[(long long)(bz + c) * p.plane + (long long)(by + b) * p.pitch + bx + a];
+        u += (double)wt * (double)F[(unsigned)((bz + c) * (int)p.plane + (by + b) * p.pitch + bx + a)];
     }
     for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
     if (lane < p.nf) {
@@ -135,10 +135,11 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     const int k1 = min(k0 + p.kz, p.n3 - R);
     const bool valid = i >= R && i <= p.n1 - 1 - R && j <= p.n2 - 1 - R;
     const int jc = min(j, p.n2 - 1);
-    const long long fo = (long long)s * p.fstride;
+    const long long fo = (long long)s * p.fstride;   // per-block (uniform) base offset
     A1 += fo;
     A2 += fo;
     A3 += fo;
+    const int plane = (int)p.plane;                   // 32-bit offsets below this base
     float *U1 = (HS ? p.H1 : p.E1) + fo;
     float *U2 = (HS ? p.H2 : p.E2) + fo;
     float *U3 = (HS ? p.H3 : p.E3) + fo;
@@ -175,6 +176,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     float *px0 = p.psx0 + s * p.psxs, *px1 = p.psx1 + s * p.psxs;
     float *py0 = p.psy0 + s * p.psys, *py1 = p.psy1 + s * p.psys;
     float *pz0 = p.psz0 + s * p.pszs, *pz1 = p.psz1 + s * p.pszs;
+    const float *ce1 = p.ce1, *ce2 = p.ce2, *ce3 = p.ce3;
 
     // dipole source of this block's source (E step only)
     int scomp = -1, sbx = 0, sby = 0, sbz = 0;
@@ -227,30 +229,32 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     float q1[L], q2[L];
 #pragma unroll
     for (int m = 0; m < L - 1; ++m) {
-        q1[m] = A1[(long long)(k0 - HL + m) * p.plane + own];
-        q2[m] = A2[(long long)(k0 - HL + m) * p.plane + own];
+        q1[m] = A1[(unsigned)((k0 - HL + m) * plane + own)];
+        q2[m] = A2[(unsigned)((k0 - HL + m) * plane + own)];
     }
 
     // staged registers of the next plane
     float f3[N3], f1[N1], f2 = 0.f, e1n, e2n;
     float un1 = 0.f, un2 = 0.f, un3 = 0.f, cn1 = 0.f, cn2 = 0.f, cn3 = 0.f;
     auto issue = [&](int k) {
-        const long long pk = (long long)k * p.plane;
+        const int pk = k * plane;
 #pragma unroll
-        for (int u = 0; u < N3; ++u) f3[u] = o3[u] >= 0 ? A3[pk + o3[u]] : 0.f;
+        for (int u = 0; u < N3; ++u) f3[u] = o3[u] >= 0 ? A3[(unsigned)(pk + o3[u])] : 0.f;
 #pragma unroll
-        for (int u = 0; u < N1; ++u) f1[u] = o1[u] >= 0 ? A1[pk + o1[u]] : 0.f;
-        if (o2 >= 0) f2 = A2[pk + o2];
-        e1n = A1[(long long)(k - HL + L - 1) * p.plane + own];
-        e2n = A2[(long long)(k - HL + L - 1) * p.plane + own];
+        for (int u = 0; u < N1; ++u) f1[u] = o1[u] >= 0 ? A1[(unsigned)(pk + o1[u])] : 0.f;
+        if (o2 >= 0) f2 = A2[(unsigned)(pk + o2)];
+        const unsigned ge = (unsigned)((k - HL + L - 1) * plane + own);
+        e1n = A1[ge];
+        e2n = A2[ge];
         if (valid) {
-            un1 = U1[pk + own];
-            un2 = U2[pk + own];
-            un3 = U3[pk + own];
+            const unsigned g = (unsigned)(pk + own);
+            un1 = U1[g];
+            un2 = U2[g];
+            un3 = U3[g];
             if (!HS) {
-                cn1 = p.ce1[pk + own];
-                cn2 = p.ce2[pk + own];
-                cn3 = p.ce3[pk + own];
+                cn1 = ce1[g];
+                cn2 = ce2[g];
+                cn3 = ce3[g];
             }
         }
     };
@@ -288,7 +292,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
                 d3a1 += cz[m] * q1[m];
             }
             if (xs) {
-                const long long id = ((long long)k * p.n2 + j) * nb2 + ix;
+                const unsigned id = (unsigned)((k * p.n2 + j) * nb2 + ix);
                 float v = bx * px0[id] + ax * d1a3;
                 px0[id] = v;
                 d1a3 += v;
@@ -297,7 +301,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
                 d1a2 += v;
             }
             if (ys) {
-                const long long id = ((long long)k * nb2 + jy) * p.pitch + i;
+                const unsigned id = (unsigned)((k * nb2 + jy) * p.pitch + i);
                 float v = by * py0[id] + ay * d2a3;
                 py0[id] = v;
                 d2a3 += v;
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
             if (k < nb || k > p.n3 - 1 - nb) {
                 const int kz = k < nb ? k : k - (p.n3 - nb2);
                 const float az = az_[k], bz = bz_[k];
-                const long long id = ((long long)kz * p.n2 + j) * p.pitch + i;
+                const unsigned id = (unsigned)((kz * p.n2 + j) * p.pitch + i);
                 float v = bz * pz0[id] + az * d3a2;
                 pz0[id] = v;
                 d3a2 += v;
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
                 d3a1 += v;
             }
             float c1 = d2a3 - d3a2, c2 = d3a1 - d1a3, c3 = d1a2 - d2a1;
-            const long long g = (long long)k * p.plane + own;
+            const unsigned g = (unsigned)(k * plane + own);
             if (HS) {
                 U1[g] = u1 - p.ch * c1;
                 U2[g] = u2 - p.ch * c2;
