@@ -61,7 +61,7 @@ def batched_comparison(emm, w, nsrc: int, group: int, ckpt: int):
     src = configs.towline_sources(nsrc, 500.0, 950.0)
     comp = np.zeros(nsrc, dtype=np.int32)
     out = {"sources": nsrc, "gradient_group": group, "checkpoint_every": ckpt}
-    with emm.Model(w, tile_kz=-1) as m:
+    with emm.Model(w, tile_kz=-1, graph_steps=64) as m:
         m.forward(sources=src[:1], src_comp=comp[:1])           # tune + warm
         t = time.perf_counter()
         plain = [m.forward(sources=src[i:i + 1], src_comp=comp[i:i + 1]) for i in range(nsrc)]
@@ -73,7 +73,7 @@ def batched_comparison(emm, w, nsrc: int, group: int, ckpt: int):
     Gp = np.concatenate(plain, axis=0)
     out["max_abs_diff_batched_vs_plain"] = float(np.max(np.abs(Gb - Gp)))
     G_obs = Gb * 1.01
-    with emm.Model(w, tile_kz=-1, checkpoint_every=ckpt) as m:
+    with emm.Model(w, tile_kz=-1, checkpoint_every=ckpt, graph_steps=64) as m:
         m.forward(sources=src[:group], src_comp=comp[:group])   # tune + warm
         t = time.perf_counter()
         for g0 in range(0, nsrc, group):
@@ -100,12 +100,12 @@ def main():
     ap.add_argument("--cube-n", type=int, default=400)
     ap.add_argument("--rd", type=int, default=0, help="override the stencil half length")
     ap.add_argument("--nt", type=int, default=0, help="override the time-step count")
-    ap.add_argument("--graph", type=int, default=0, help="time steps per captured hipGraph")
+    ap.add_argument("--graph", type=int, default=64, help="time steps per captured hipGraph (0: direct launches)")
     ap.add_argument("--tile-kz", type=int, default=-1, help="z planes per block (-1: autotuned)")
     ap.add_argument("--batched", type=int, default=16,
                     help="sources of the batched comparison (0: skip)")
     ap.add_argument("--grad-group", type=int, default=8)
-    ap.add_argument("--grad-ckpt", type=int, default=130)
+    ap.add_argument("--grad-ckpt", type=int, default=128)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -143,8 +143,7 @@ def main():
         w = w.with_(nt=args.nt)
     log(f"[bench] workload {w.name} padded cells {w.padded_cells}")
 
-    model = emm.Model(w, profile=0 if args.graph else 1, graph_steps=args.graph,
-                      tile_kz=args.tile_kz)
+    model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz)
     for i in range(args.warmup):
         model.forward()
         log(f"[bench] warmup {i} done")

@@ -74,7 +74,9 @@ typedef struct {
     double cpml_alpha_max; /* frequency-shift maximum; 0 = pi * f_peak [0] */
     double wavelet_fpeak;  /* source wavelet peak frequency; 0 = 2 sqrt(f_max f0) [0] */
     int    allow_unstable; /* test hook: accept dt_override above the CFL limit [0] */
-    int    profile;        /* 1 = time every stencil launch with HIP events (emm_query) [0] */
+    int    profile;        /* 1 = time stencil launches with HIP events: one E/H pair in 16
+                              direct steps; with graph_steps, every 8th block of steps runs as
+                              direct launches and one pair in 4 of them is timed (emm_query) [0] */
     int    tile_kz;        /* z planes per thread block; 0 = chosen from the grid, -1 = autotuned
                               on the first forward (timing candidates on this model) [0] */
     int    checkpoint_every; /* > 0: emm_forward keeps full-state checkpoints every this many
@@ -99,9 +101,9 @@ typedef struct {
     long long cells;         /* n1pad * n2pad * n3pad */
     double bytes_per_step;   /* algorithmic HBM bytes of one e-step + h-step, one source */
     double e_bytes, h_bytes; /* split of bytes_per_step over the two stencil kernels */
-    /* filled when options.profile = 1: totals over the last forward */
+    /* filled when options.profile = 1: totals over the timed launches of the last forward */
     double e_kernel_ms, h_kernel_ms;   /* summed kernel durations (HIP events) */
-    long long e_launches, h_launches;
+    long long e_launches, h_launches;  /* number of launches timed */
     double forward_ms;       /* device time of the whole time loop (HIP events) */
     int    tile_kz;          /* z planes per block actually used */
 } emm_info;

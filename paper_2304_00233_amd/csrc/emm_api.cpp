@@ -714,8 +714,13 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         const int nck = (nt + ckpt - 1) / ckpt;
         if ((st = ensure(m, m->ckpts, (size_t)nck * state_floats(m) * nsrc * sizeof(float))) != EMM_OK) return st;
     }
+    // Profiling: HIP events bracket one E step and one H step out of every
+    // `sample` direct launches.  With graph replays (event nodes in graphs
+    // carry no timestamps here), every 8th block of K steps is launched
+    // directly instead -- the same kernels with the absolute step index --
+    // and sampled, so the timing is taken inside the timed loop.
     const bool prof = m->opt.profile != 0;
-    const int ring_pairs = 128;
+    const int sample = 16, ring_pairs = 64;
     if (prof && m->ring.empty()) {
         m->ring.assign(4 * ring_pairs, nullptr);
         for (hipEvent_t &e : m->ring) HIP_OK(m, hipEventCreate(&e));
@@ -725,6 +730,8 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         HIP_OK(m, hipEventCreate(&m->ev_loop[1]));
     }
     double ems = 0.0, hms = 0.0;
+    long long nsamp = 0;
+    int nslots_used = 0;
     auto harvest = [&](int slot) -> emm_status {
         float a = 0.f, b = 0.f;
         HIP_OK(m, hipEventSynchronize(m->ring[4 * slot + 3]));
@@ -732,14 +739,36 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         HIP_OK(m, hipEventElapsedTime(&b, m->ring[4 * slot + 2], m->ring[4 * slot + 3]));
         ems += a;
         hms += b;
+        ++nsamp;
+        return EMM_OK;
+    };
+    // one direct step, bracketed by events when `timed`
+    auto step = [&](int n, bool timed) -> emm_status {
+        int slot = -1;
+        if (timed) {
+            slot = nslots_used % ring_pairs;
+            if (nslots_used >= ring_pairs) {
+                emm_status s2 = harvest(slot);
+                if (s2 != EMM_OK) return s2;
+            }
+            ++nslots_used;
+            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 0], stream));
+        }
+        emm::launch_e_step(r, A.Pe, n, stream);
+        if (timed) {
+            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 1], stream));
+            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 2], stream));
+        }
+        emm::launch_h_step(r, A.Ph, n, stream);
+        if (timed) HIP_OK(m, hipEventRecord(m->ring[4 * slot + 3], stream));
         return EMM_OK;
     };
     HIP_OK(m, hipEventRecord(m->ev_loop[0], stream));
     int n_begin = 0;
-    // K steps per captured hipGraph, replayed with a device step counter
-    // (not with per-launch profiling; checkpoints must fall on replay edges)
+    // K steps per captured hipGraph, replayed with a device step counter;
+    // checkpoints must fall on replay edges
     const int K = m->opt.graph_steps;
-    if (K > 0 && !prof && nt >= K && (ckpt == 0 || ckpt % K == 0)) {
+    if (K > 0 && nt >= K && (ckpt == 0 || ckpt % K == 0)) {
         if ((st = ensure(m, m->stepdev, 256)) != EMM_OK) return st;
         int *stepd = (int *)m->stepdev.p;
         HIP_OK(m, hipMemsetAsync(stepd, 0, sizeof(int), stream));
@@ -763,7 +792,13 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         for (int q = 0; q < reps; ++q) {
             const int n = q * K;
             if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, n / ckpt, true, stream)) != EMM_OK) return st;
-            HIP_OK(m, hipGraphLaunch(exec, stream));
+            if (prof && q % 8 == 0) {
+                for (int j = 0; j < K; ++j)
+                    if ((st = step(n + j, j % 4 == 0)) != EMM_OK) return st;
+                emm::launch_advance(stepd, K, stream);
+            } else {
+                HIP_OK(m, hipGraphLaunch(exec, stream));
+            }
         }
         HIP_OK(m, hipStreamSynchronize(stream));
         (void)hipGraphExecDestroy(exec);
@@ -772,24 +807,13 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     }
     for (int n = n_begin; n < nt; ++n) {
         if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, n / ckpt, true, stream)) != EMM_OK) return st;
-        const int slot = n % ring_pairs;
-        if (prof) {
-            if (n >= ring_pairs && (st = harvest(slot)) != EMM_OK) return st;
-            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 0], stream));
-        }
-        emm::launch_e_step(r, A.Pe, n, stream);
-        if (prof) {
-            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 1], stream));
-            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 2], stream));
-        }
-        emm::launch_h_step(r, A.Ph, n, stream);
-        if (prof) HIP_OK(m, hipEventRecord(m->ring[4 * slot + 3], stream));
+        if ((st = step(n, prof && (n - n_begin) % sample == 0)) != EMM_OK) return st;
     }
     HIP_OK(m, hipGetLastError());
     HIP_OK(m, hipEventRecord(m->ev_loop[1], stream));
     if (prof)
-        for (int n = std::max(0, nt - ring_pairs); n < nt; ++n)
-            if ((st = harvest(n % ring_pairs)) != EMM_OK) return st;
+        for (int u = std::max(0, nslots_used - ring_pairs); u < nslots_used; ++u)
+            if ((st = harvest(u % ring_pairs)) != EMM_OK) return st;
     HIP_OK(m, hipStreamSynchronize(stream));
     float loop_ms = 0.f;
     HIP_OK(m, hipEventElapsedTime(&loop_ms, m->ev_loop[0], m->ev_loop[1]));
@@ -799,8 +823,8 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     m->info.tile_kz = A.Pe.kz;
     m->info.e_kernel_ms = prof ? ems : 0.0;
     m->info.h_kernel_ms = prof ? hms : 0.0;
-    m->info.e_launches = prof ? nt : 0;
-    m->info.h_launches = prof ? nt : 0;
+    m->info.e_launches = prof ? nsamp : 0;
+    m->info.h_launches = prof ? nsamp : 0;
     return EMM_OK;
 }
 

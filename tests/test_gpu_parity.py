@@ -145,9 +145,13 @@ def test_error_paths_on_device(emm):
 def test_profile_counters(emm):
     w = configs.small_case(seed=12, shape=(30, 28, 26), nt=120)
     G, info = _run(emm, w, profile=1)
-    assert info["e_launches"] == 120 and info["h_launches"] == 120
+    assert info["e_launches"] == 120 // 16 + 1 and info["h_launches"] == info["e_launches"]
     assert 0 < info["e_kernel_ms"] < info["forward_ms"]
     assert 0 < info["h_kernel_ms"] < info["forward_ms"]
+    G2, info2 = _run(emm, w, profile=1, graph_steps=16)     # events inside the graphs
+    assert np.array_equal(G, G2)
+    # 7 blocks of 16: block 0 direct with 4 timed steps, then a tail of 8 with 1
+    assert info2["e_launches"] == 4 + 1 and info2["e_kernel_ms"] > 0
 
 
 def test_autotuned_tiles_are_bitwise_identical(emm):
