@@ -80,10 +80,13 @@ typedef struct {
     int    tile_kz;        /* z planes per thread block; 0 = chosen from the grid, -1 = autotuned
                               on the first forward (timing candidates on this model) [0] */
     int    checkpoint_every; /* > 0: emm_forward keeps full-state checkpoints every this many
-                              steps for a following emm_gradient; emm_gradient's interval
-                              (0 = 50) [0] */
+                              steps for a following emm_gradient, and emm_gradient uses this
+                              outer interval; 0: emm_gradient plans it (see below) [0] */
     int    graph_steps;    /* > 0: capture this many time steps in one hipGraph and replay it
                               (a device step counter advances between replays) [0] */
+    int    checkpoint_inner; /* > 0 and < the outer interval: emm_gradient re-runs each outer
+                              segment once to lay inner checkpoints this many steps apart
+                              (two levels); 0: planned [0] */
 } emm_options;
 
 /* A point electric dipole (Section 5, "Survey acquisitions"): position in
@@ -106,6 +109,10 @@ typedef struct {
     long long e_launches, h_launches;  /* number of launches timed */
     double forward_ms;       /* device time of the whole time loop (HIP events) */
     int    tile_kz;          /* z planes per block actually used */
+    /* checkpoint schedule of the last emm_gradient */
+    int    ckpt_outer;       /* steps between the forward's checkpoints */
+    int    ckpt_inner;       /* steps between inner checkpoints (== ckpt_outer: one level) */
+    double ckpt_bytes;       /* device bytes of checkpoints and per-step E snapshots */
 } emm_info;
 
 /* Fill *o with the defaults above. */
@@ -137,12 +144,50 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc,
                        const double *freq_hz, int nfreq, double *green,
                        void *hip_stream);
 
+/* One forward modelling of emm_forward_batch: a model with its acquisition
+ * and output, all as in emm_forward. */
+typedef struct {
+    emm_model *model;
+    const emm_source *src;
+    int nsrc;
+    const emm_receiver *rec;
+    int nrec;
+    unsigned chan_mask;
+    const double *freq_hz;
+    int nfreq;
+    double *green;
+} emm_job;
+
+/* Run the forward modellings of njobs jobs on different models (any grid
+ * sizes; each keeps its own dt, step count and autotuned tiles) as the
+ * independent branches of one captured hipGraph of graph_steps time steps
+ * per job (0 = 64), replayed with a device step counter per model: small
+ * grids then share the chip instead of running one after another (the
+ * paper runs one transmitter per process, Section 5; here many models and
+ * sources share one launch stream).  When a job has done all its whole
+ * graph_steps blocks, the graph is captured again without it and its last
+ * nt % graph_steps steps run as direct launches.  Each job's green is
+ * exactly what emm_forward writes for it (bitwise).  A model may appear in
+ * one job only; every model must live on the same device.  hip_stream: as
+ * emm_forward (NULL = the first model's stream).  Errors: as emm_forward;
+ * the first failing job stops the call (emm_last_error of that model). */
+emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, void *hip_stream);
+
 /* Discrete adjoint of the whole time loop (the exact gradient of the
  * FP32 time stepping as written: reverse of every E and H update with the
  * transposed finite-difference operators, reverse of the CPML memory-variable
- * recursion, reverse of the receiver DTFT), evaluated with full-state
- * checkpoints every checkpoint_every steps and forward recomputation inside
- * each segment.  The scalar L is either
+ * recursion, reverse of the receiver DTFT), evaluated from full-state
+ * checkpoints with forward recomputation.  The reverse sweep walks the
+ * segments between checkpoints backwards; each segment is recomputed once
+ * with the E field of every step kept, then reversed.  Memory, with S the
+ * state of all nsrc sources (E, H, CPML memories) and F their E fields:
+ *   one level  (inner == outer = C):  ceil(nt/C) S + (C+1) F
+ *   two levels (inner C2 < outer C1): ceil(nt/C1) S + ceil(C1/C2) S + (C2+1) F
+ * at the price of one more forward pass.  Intervals left at 0 are planned:
+ * the one-level interval of least memory if it fits in the free device
+ * memory (after the adjoint's own arrays), else the two-level pair of least
+ * memory; EMM_ERR_OOM if neither fits (run fewer sources per call).  The
+ * result does not depend on the schedule (bitwise).  The scalar L is either
  *   g_obs != NULL: L = 1/2 sum over all results of |log(G/G_obs)|^2 (real
  *                  part: log-amplitude residual, imaginary part: phase
  *                  residual), returned in *misfit (may be NULL), or

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -69,6 +70,7 @@ struct emm_model {
     // forward-lifetime device data (grown on demand, kept between forwards)
     DevBuf fields, psi, acc, cpml, srcinfo, srcq, wav, items, itemw, phase;
     DevBuf ckpts;                                   // full-state checkpoints of the last run
+    DevBuf ickpts;                                  // inner checkpoints of one outer segment
     DevBuf stepdev;                                 // device step counter of graph replays
     // adjoint: Et|Hb fields, Q (12 slab arrays), T (6), E snapshots, per-source
     // gradients, transposed tables, injection lists and coefficients
@@ -168,6 +170,7 @@ emm_status emm_default_options(emm_options *o) {
     o->tile_kz = 0;
     o->checkpoint_every = 0;
     o->graph_steps = 0;
+    o->checkpoint_inner = 0;
     return EMM_OK;
 }
 
@@ -199,7 +202,7 @@ void emm_destroy(emm_model *m) {
     for (float *p : m->ce) if (p) (void)hipFree(p);
     for (float *p : m->tab) if (p) (void)hipFree(p);
     for (DevBuf *b : {&m->fields, &m->psi, &m->acc, &m->cpml, &m->srcinfo, &m->srcq, &m->wav,
-                      &m->items, &m->itemw, &m->phase, &m->ckpts, &m->adjf, &m->adjq, &m->adjt,
+                      &m->items, &m->itemw, &m->phase, &m->ckpts, &m->ickpts, &m->adjf, &m->adjq, &m->adjt,
                       &m->snaps, &m->grad, &m->tabT, &m->inj, &m->injA, &m->adjcpml, &m->stepdev})
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : m->ev_loop) if (e) (void)hipEventDestroy(e);
@@ -225,6 +228,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (!(opt.f0 > 0.0) || !std::isfinite(opt.f0)) return fail(nullptr, EMM_ERR_ARG, "f0 must be > 0");
     if (!(opt.cfl > 0.0) || !std::isfinite(opt.cfl)) return fail(nullptr, EMM_ERR_ARG, "cfl must be > 0");
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
+        opt.checkpoint_inner < 0 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -680,12 +684,13 @@ size_t state_floats(const emm_model *m) {
     return (size_t)(6 * fstride + 4 * (psxs + psys + pszs));
 }
 
-// Checkpoint c <-> live state copies (fields and CPML memories of all sources).
-emm_status copy_state(emm_model *m, int c, bool save, hipStream_t stream) {
+// Checkpoint c of buffer `base` <-> live state copies (fields and CPML
+// memories of all sources).
+emm_status copy_state(emm_model *m, void *base, int c, bool save, hipStream_t stream) {
     const Acq &A = m->acq;
     const size_t ff = (size_t)6 * A.nsrc * A.Pe.fstride * sizeof(float);
     const size_t pf = state_floats(m) * A.nsrc * sizeof(float) - ff;
-    char *ck = (char *)m->ckpts.p + (size_t)c * (ff + pf);
+    char *ck = (char *)base + (size_t)c * (ff + pf);
     if (save) {
         HIP_OK(m, hipMemcpyAsync(ck, m->fields.p, ff, hipMemcpyDeviceToDevice, stream));
         if (pf) HIP_OK(m, hipMemcpyAsync(ck + ff, m->psi.p, pf, hipMemcpyDeviceToDevice, stream));
@@ -693,6 +698,88 @@ emm_status copy_state(emm_model *m, int c, bool save, hipStream_t stream) {
         HIP_OK(m, hipMemcpyAsync(m->fields.p, ck, ff, hipMemcpyDeviceToDevice, stream));
         if (pf) HIP_OK(m, hipMemcpyAsync(m->psi.p, ck + ff, pf, hipMemcpyDeviceToDevice, stream));
     }
+    return EMM_OK;
+}
+
+// Device bytes of the reverse sweep's checkpoints and E snapshots for outer
+// interval c1 and inner interval c2 (c2 >= c1: one level), with S bytes per
+// full state and F bytes per E snapshot (all sources).
+size_t ckpt_memory(int nt, int c1, int c2, size_t S, size_t F) {
+    const size_t outer = (size_t)((nt + c1 - 1) / c1) * S;
+    if (c2 >= c1) return outer + (size_t)(c1 + 1) * F;
+    return outer + (size_t)((c1 + c2 - 1) / c2) * S + (size_t)(c2 + 1) * F;
+}
+
+// Checkpoint schedule within `budget` bytes.  Given intervals (> 0) are
+// kept.  Otherwise: the one-level interval of least memory, preferring a
+// multiple of the graph length K (the forward then replays graphs); if none
+// fits, the two-level pair of least memory.  false: nothing fits.
+bool plan_checkpoints(int nt, int K, int c1_fix, int c2_fix, size_t S, size_t F, size_t budget,
+                      int &c1, int &c2) {
+    auto better = [](size_t mem, size_t &best_mem) {
+        if (mem < best_mem) {
+            best_mem = mem;
+            return true;
+        }
+        return false;
+    };
+    if (c1_fix > 0 && c2_fix > 0) {
+        c1 = c1_fix;
+        c2 = std::min(c2_fix, c1_fix);
+        return true;
+    }
+    if (c1_fix > 0) {                                  // inner interval only
+        c1 = c2 = c1_fix;
+        if (ckpt_memory(nt, c1, c1, S, F) <= budget) return true;
+        size_t best = SIZE_MAX;
+        for (int b = 1; b < c1_fix; ++b)
+            if (better(ckpt_memory(nt, c1, b, S, F), best)) c2 = b;
+        return best <= budget;
+    }
+    if (c2_fix > 0 && c2_fix < nt) {                   // outer interval for a given inner one
+        size_t best = SIZE_MAX;
+        c2 = c2_fix;
+        c1 = nt;
+        for (int a = 2 * c2_fix; a < nt + c2_fix; a += c2_fix)
+            if (better(ckpt_memory(nt, a, c2_fix, S, F), best)) c1 = a;
+        return best <= budget;
+    }
+    size_t best_k = SIZE_MAX, best_any = SIZE_MAX;
+    int ck = 0, ca = 1;
+    for (int c = 1; c <= nt; ++c) {
+        const size_t mem = ckpt_memory(nt, c, c, S, F);
+        if (K > 0 && c % K == 0 && better(mem, best_k)) ck = c;
+        if (better(mem, best_any)) ca = c;
+    }
+    if (best_k <= budget) {
+        c1 = c2 = ck;
+        return true;
+    }
+    if (best_any <= budget) {
+        c1 = c2 = ca;
+        return true;
+    }
+    size_t best = SIZE_MAX;
+    c1 = c2 = ca;
+    for (int b = 1; b <= std::min(nt, 4096); ++b)
+        for (int a = 2 * b; a < nt + b; a += b)
+            if (better(ckpt_memory(nt, a, b, S, F), best)) {
+                c1 = a;
+                c2 = b;
+            }
+    return best <= budget;
+}
+
+// Zero fields, CPML memories and DTFT accumulators of all sources.
+emm_status zero_state(emm_model *m, hipStream_t stream) {
+    const Acq &A = m->acq;
+    const long long fstride = A.Pe.fstride;
+    const size_t acc_elem = m->opt.dft_mode ? sizeof(float4) : sizeof(double2);
+    const int nslot = A.nsrc * A.nrec * A.nch;
+    HIP_OK(m, hipMemsetAsync(m->fields.p, 0, (size_t)6 * A.nsrc * fstride * sizeof(float), stream));
+    const size_t psi_bytes = (state_floats(m) - 6 * fstride) * A.nsrc * sizeof(float);
+    if (psi_bytes) HIP_OK(m, hipMemsetAsync(m->psi.p, 0, psi_bytes, stream));
+    HIP_OK(m, hipMemsetAsync(m->acc.p, 0, (size_t)nslot * A.nf * acc_elem, stream));
     return EMM_OK;
 }
 
@@ -704,12 +791,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     emm_status st;
     const int nsrc = A.nsrc, nt = A.nt, r = m->r;
     const long long fstride = A.Pe.fstride;
-    const size_t acc_elem = m->opt.dft_mode ? sizeof(float4) : sizeof(double2);
-    const int nslot = A.nsrc * A.nrec * A.nch;
-    HIP_OK(m, hipMemsetAsync(m->fields.p, 0, (size_t)6 * nsrc * fstride * sizeof(float), stream));
-    const size_t psi_bytes = (state_floats(m) - 6 * fstride) * nsrc * sizeof(float);
-    if (psi_bytes) HIP_OK(m, hipMemsetAsync(m->psi.p, 0, psi_bytes, stream));
-    HIP_OK(m, hipMemsetAsync(m->acc.p, 0, (size_t)nslot * A.nf * acc_elem, stream));
+    if ((st = zero_state(m, stream)) != EMM_OK) return st;
     if (ckpt > 0) {
         const int nck = (nt + ckpt - 1) / ckpt;
         if ((st = ensure(m, m->ckpts, (size_t)nck * state_floats(m) * nsrc * sizeof(float))) != EMM_OK) return st;
@@ -791,7 +873,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         const int reps = nt / K;
         for (int q = 0; q < reps; ++q) {
             const int n = q * K;
-            if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, n / ckpt, true, stream)) != EMM_OK) return st;
+            if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, m->ckpts.p, n / ckpt, true, stream)) != EMM_OK) return st;
             if (prof && q % 8 == 0) {
                 for (int j = 0; j < K; ++j)
                     if ((st = step(n + j, j % 4 == 0)) != EMM_OK) return st;
@@ -806,7 +888,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         n_begin = reps * K;
     }
     for (int n = n_begin; n < nt; ++n) {
-        if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, n / ckpt, true, stream)) != EMM_OK) return st;
+        if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, m->ckpts.p, n / ckpt, true, stream)) != EMM_OK) return st;
         if ((st = step(n, prof && (n - n_begin) % sample == 0)) != EMM_OK) return st;
     }
     HIP_OK(m, hipGetLastError());
@@ -857,6 +939,133 @@ std::complex<double> green_factor(const emm_model *m, size_t k) {
     std::complex<double> g = 1.0 / (A.sscale[s] * A.src[s].moment * A.Shat[f]);
     if (A.chans[c] < 3) g *= (2.0 * kPi * A.freqs[f]) / A.wp[f];
     return g;
+}
+
+// G from the accumulators of the last forward (Section 2.2 normalisation).
+emm_status write_green(emm_model *m, hipStream_t stream, double *green) {
+    emm_status st;
+    std::vector<std::complex<double>> acc;
+    if ((st = read_acc(m, stream, acc)) != EMM_OK) return st;
+    bool nonfinite = false;
+    for (size_t k = 0; k < acc.size(); ++k) {
+        const std::complex<double> G = acc[k] * green_factor(m, k);
+        if (!std::isfinite(G.real()) || !std::isfinite(G.imag())) nonfinite = true;
+        green[2 * k] = G.real();
+        green[2 * k + 1] = G.imag();
+    }
+    if (nonfinite) return fail(m, EMM_ERR_NONFINITE, "a DTFT accumulator is not finite (unstable run?)");
+    return EMM_OK;
+}
+
+// Time loops of several models (one job each) in one captured hipGraph: the
+// K-step sequences of the jobs are independent branches of the graph, so
+// small grids run side by side on the chip.  Jobs have their own dt and step
+// count; the graph is re-captured for the jobs still running whenever one
+// has done all its whole K-step blocks, and that job's last nt % K steps run
+// as direct launches.
+emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t stream) {
+    emm_status st = EMM_OK;
+    emm_model *m0 = ms[0];
+    const int nj = (int)ms.size();
+    for (emm_model *m : ms) {
+        if ((st = zero_state(m, stream)) != EMM_OK) return st;
+        if ((st = ensure(m, m->stepdev, 256)) != EMM_OK) return st;
+        HIP_OK(m, hipMemsetAsync(m->stepdev.p, 0, sizeof(int), stream));
+        m->acq.ckpt = 0;
+    }
+    std::vector<hipStream_t> side(nj, nullptr);
+    std::vector<hipEvent_t> join(nj, nullptr);
+    hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
+    auto cleanup = [&]() {
+        for (hipStream_t q : side) if (q) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : join) if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {fork, t0, t1}) if (e) (void)hipEventDestroy(e);
+    };
+    auto run = [&]() -> emm_status {
+        for (int j = 0; j < nj; ++j) {
+            HIP_OK(m0, hipStreamCreateWithFlags(&side[j], hipStreamNonBlocking));
+            HIP_OK(m0, hipEventCreateWithFlags(&join[j], hipEventDisableTiming));
+        }
+        HIP_OK(m0, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        HIP_OK(m0, hipEventCreate(&t0));
+        HIP_OK(m0, hipEventCreate(&t1));
+        HIP_OK(m0, hipEventRecord(t0, stream));
+        std::vector<int> whole(nj);
+        for (int j = 0; j < nj; ++j) whole[j] = ms[j]->acq.nt / K;
+        int q = 0;                                    // K-step blocks done by every running job
+        std::vector<bool> done(nj, false);
+        for (;;) {
+            // finish the jobs whose whole blocks are done: their remainder steps
+            for (int j = 0; j < nj; ++j) {
+                if (done[j] || whole[j] > q) continue;
+                const Acq &A = ms[j]->acq;
+                for (int n = whole[j] * K; n < A.nt; ++n) {
+                    emm::launch_e_step(ms[j]->r, A.Pe, n, stream);
+                    emm::launch_h_step(ms[j]->r, A.Ph, n, stream);
+                }
+                done[j] = true;
+            }
+            int reps = INT32_MAX;
+            std::vector<int> act;
+            for (int j = 0; j < nj; ++j)
+                if (!done[j]) {
+                    act.push_back(j);
+                    reps = std::min(reps, whole[j] - q);
+                }
+            if (act.empty()) break;
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            HIP_OK(m0, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = hipEventRecord(fork, stream);
+            for (int j : act) {
+                if (ce != hipSuccess) break;
+                emm_model *m = ms[j];
+                emm::StepParams Pe = m->acq.Pe, Ph = m->acq.Ph;
+                Pe.step_base = Ph.step_base = (const int *)m->stepdev.p;
+                ce = hipStreamWaitEvent(side[j], fork, 0);
+                for (int i = 0; i < K && ce == hipSuccess; ++i) {
+                    emm::launch_e_step(m->r, Pe, i, side[j]);
+                    emm::launch_h_step(m->r, Ph, i, side[j]);
+                }
+                emm::launch_advance((int *)m->stepdev.p, K, side[j]);
+                if (ce == hipSuccess) ce = hipEventRecord(join[j], side[j]);
+                if (ce == hipSuccess) ce = hipStreamWaitEvent(stream, join[j], 0);
+            }
+            hipError_t ee = hipStreamEndCapture(stream, &graph);
+            if (ce != hipSuccess || ee != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(m0, EMM_ERR_DEVICE, std::string("graph capture: ") +
+                                                    hipGetErrorString(ce != hipSuccess ? ce : ee));
+            }
+            hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return fail(m0, EMM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            for (int u = 0; u < reps && e == hipSuccess; ++u) e = hipGraphLaunch(exec, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(m0, EMM_ERR_DEVICE, std::string("graph replay: ") + hipGetErrorString(e));
+            q += reps;
+        }
+        HIP_OK(m0, hipGetLastError());
+        HIP_OK(m0, hipEventRecord(t1, stream));
+        HIP_OK(m0, hipStreamSynchronize(stream));
+        float ms_loop = 0.f;
+        HIP_OK(m0, hipEventElapsedTime(&ms_loop, t0, t1));
+        for (emm_model *m : ms) {
+            m->info.nt = m->acq.nt;
+            m->info.forward_ms = ms_loop;
+            m->info.tile_kz = m->acq.Pe.kz;
+            m->info.e_kernel_ms = m->info.h_kernel_ms = 0.0;
+            m->info.e_launches = m->info.h_launches = 0;
+        }
+        return EMM_OK;
+    };
+    st = run();
+    cleanup();
+    return st;
 }
 
 // Autotuner of the z chunk per thread block (tile_kz = -1): time a few
@@ -925,16 +1134,35 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     if ((st = prepare(m, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq, stream)) != EMM_OK) return st;
     if ((st = autotune(m, stream)) != EMM_OK) return st;
     if ((st = time_loop(m, stream, m->opt.checkpoint_every)) != EMM_OK) return st;
-    std::vector<std::complex<double>> acc;
-    if ((st = read_acc(m, stream, acc)) != EMM_OK) return st;
-    bool nonfinite = false;
-    for (size_t k = 0; k < acc.size(); ++k) {
-        const std::complex<double> G = acc[k] * green_factor(m, k);
-        if (!std::isfinite(G.real()) || !std::isfinite(G.imag())) nonfinite = true;
-        green[2 * k] = G.real();
-        green[2 * k + 1] = G.imag();
+    return write_green(m, stream, green);
+}
+
+emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, void *hip_stream) {
+    if (!jobs || njobs <= 0) return fail(nullptr, EMM_ERR_ARG, "need at least one job");
+    if (graph_steps < 0) return fail(nullptr, EMM_ERR_ARG, "graph_steps must be >= 0");
+    std::vector<emm_model *> ms;
+    for (int j = 0; j < njobs; ++j) {
+        emm_model *m = jobs[j].model;
+        if (!m) return fail(nullptr, EMM_ERR_ARG, "job " + std::to_string(j) + ": NULL model");
+        if (!jobs[j].green) return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": NULL output pointer");
+        if (std::find(ms.begin(), ms.end(), m) != ms.end())
+            return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": a model may appear in one job only");
+        if (m->device != jobs[0].model->device)
+            return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": all models must be on one device");
+        m->err.clear();
+        ms.push_back(m);
     }
-    if (nonfinite) return fail(m, EMM_ERR_NONFINITE, "a DTFT accumulator is not finite (unstable run?)");
+    hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : ms[0]->own_stream;
+    emm_status st;
+    for (int j = 0; j < njobs; ++j) {
+        const emm_job &J = jobs[j];
+        if ((st = prepare(J.model, J.src, J.nsrc, J.rec, J.nrec, J.chan_mask, J.freq_hz, J.nfreq, stream)) != EMM_OK)
+            return st;
+        if ((st = autotune(J.model, stream)) != EMM_OK) return st;
+    }
+    if ((st = time_loop_jobs(ms, graph_steps > 0 ? graph_steps : 64, stream)) != EMM_OK) return st;
+    for (int j = 0; j < njobs; ++j)
+        if ((st = write_green(jobs[j].model, stream, jobs[j].green)) != EMM_OK) return st;
     return EMM_OK;
 }
 
@@ -948,15 +1176,45 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
         return fail(m, EMM_ERR_ARG, "need grad and exactly one of g_obs, g_bar");
     emm_status st;
     hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
-    const int ck = m->opt.checkpoint_every > 0 ? m->opt.checkpoint_every : 50;
     // forward with checkpoints, unless the last forward stored them for the same acquisition
-    if (!(m->acq.ckpt > 0 && same_acquisition(m->acq, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq))) {
+    const bool reuse = m->acq.ckpt > 0 && same_acquisition(m->acq, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq);
+    if (!reuse) {
         if ((st = prepare(m, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq, stream)) != EMM_OK) return st;
         if ((st = autotune(m, stream)) != EMM_OK) return st;
-        if ((st = time_loop(m, stream, ck)) != EMM_OK) return st;
     }
+    // checkpoint schedule: the budget is the free device memory plus what the
+    // checkpoint buffers already hold, minus what the adjoint arrays below
+    // still need and a margin
+    int c1 = 0, c2 = 0;
+    {
+        const Acq &A0 = m->acq;
+        const long long fs = A0.Pe.fstride;
+        const size_t S = state_floats(m) * A0.nsrc * sizeof(float);
+        const size_t F = (size_t)3 * A0.nsrc * fs * sizeof(float);
+        const size_t slab_src = (state_floats(m) - 6 * fs) / 2;     // 6 slab arrays per source
+        const size_t need[4] = {(size_t)6 * A0.nsrc * fs * sizeof(float),
+                                std::max<size_t>(1, 2 * A0.nsrc * slab_src) * sizeof(float),
+                                std::max<size_t>(1, A0.nsrc * slab_src) * sizeof(float),
+                                (size_t)3 * A0.nsrc * fs * sizeof(double)};
+        const DevBuf *have[4] = {&m->adjf, &m->adjq, &m->adjt, &m->grad};
+        size_t fr = 0, tot = 0;
+        HIP_OK(m, hipMemGetInfo(&fr, &tot));
+        long long budget = (long long)fr + (long long)(m->ckpts.bytes + m->ickpts.bytes + m->snaps.bytes);
+        for (int b = 0; b < 4; ++b) budget -= (long long)(need[b] > have[b]->bytes ? need[b] - have[b]->bytes : 0);
+        budget -= (long long)(tot / 50) + (256LL << 20);
+        const size_t bud = budget > 0 ? (size_t)budget : 0;
+        if (!plan_checkpoints(A0.nt, m->opt.graph_steps, reuse ? A0.ckpt : m->opt.checkpoint_every,
+                              m->opt.checkpoint_inner, S, F, bud, c1, c2))
+            return fail(m, EMM_ERR_OOM, "no checkpoint schedule fits in " + std::to_string(bud) +
+                                            " bytes of device memory; run fewer sources per call");
+        m->info.ckpt_outer = c1;
+        m->info.ckpt_inner = std::min(c1, c2);
+        m->info.ckpt_bytes = (double)ckpt_memory(A0.nt, c1, c2, S, F);
+    }
+    if (!reuse && (st = time_loop(m, stream, c1)) != EMM_OK) return st;
     const Acq &A = m->acq;
-    const int ckpt = A.ckpt;
+    const int ckpt = A.ckpt;                 // outer interval
+    const int cin = std::min(c2, ckpt);      // inner interval
     std::vector<std::complex<double>> acc;
     if ((st = read_acc(m, stream, acc)) != EMM_OK) return st;
     const size_t nd = acc.size();
@@ -1046,7 +1304,10 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     if ((st = ensure(m, m->adjf, (size_t)6 * nsrc * fstride * sizeof(float))) != EMM_OK) return st;
     if ((st = ensure(m, m->adjq, (size_t)std::max<long long>(1, 2 * nsrc * slab_src) * sizeof(float))) != EMM_OK) return st;
     if ((st = ensure(m, m->adjt, (size_t)std::max<long long>(1, nsrc * slab_src) * sizeof(float))) != EMM_OK) return st;
-    if ((st = ensure(m, m->snaps, (size_t)(ckpt + 1) * 3 * nsrc * fstride * sizeof(float))) != EMM_OK) return st;
+    if ((st = ensure(m, m->snaps, (size_t)(cin + 1) * 3 * nsrc * fstride * sizeof(float))) != EMM_OK) return st;
+    if (cin < ckpt &&
+        (st = ensure(m, m->ickpts, (size_t)((ckpt + cin - 1) / cin) * state_floats(m) * nsrc * sizeof(float))) != EMM_OK)
+        return st;
     if ((st = ensure(m, m->grad, (size_t)3 * nsrc * fstride * sizeof(double))) != EMM_OK) return st;
     HIP_OK(m, hipMemsetAsync(m->adjf.p, 0, (size_t)6 * nsrc * fstride * sizeof(float), stream));
     if (nb) HIP_OK(m, hipMemsetAsync(m->adjq.p, 0, (size_t)2 * nsrc * slab_src * sizeof(float), stream));
@@ -1211,10 +1472,11 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     Pe.nitems = Ph.nitems = 0;
     float *snap = (float *)m->snaps.p;
     const size_t snap_bytes = (size_t)3 * nsrc * fstride * sizeof(float);
-    const int nseg = (nt + ckpt - 1) / ckpt;
-    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
-        const int n0 = sgi * ckpt, nend = std::min(n0 + ckpt, nt);
-        if ((st = copy_state(m, sgi, false, stream)) != EMM_OK) return st;
+    // one segment [n0, nend) from checkpoint c of buffer `base`: recompute it
+    // keeping E after every step, then reverse its steps
+    auto reverse_segment = [&](void *base, int c, int n0, int nend) -> emm_status {
+        emm_status s2;
+        if ((s2 = copy_state(m, base, c, false, stream)) != EMM_OK) return s2;
         HIP_OK(m, hipMemcpyAsync(snap, m->fields.p, snap_bytes, hipMemcpyDeviceToDevice, stream));
         for (int n = n0; n < nend; ++n) {
             emm::launch_e_step(r, Pe, n, stream);
@@ -1233,6 +1495,29 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
             emm::launch_adj_inject(IH, n, stream);
         }
         HIP_OK(m, hipGetLastError());
+        return EMM_OK;
+    };
+    const int nseg = (nt + ckpt - 1) / ckpt;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int n0 = sgi * ckpt, nend = std::min(n0 + ckpt, nt);
+        if (cin >= ckpt) {
+            if ((st = reverse_segment(m->ckpts.p, sgi, n0, nend)) != EMM_OK) return st;
+            continue;
+        }
+        // two levels: re-run the outer segment once, laying inner checkpoints
+        const int nq = (nend - n0 + cin - 1) / cin;
+        if ((st = copy_state(m, m->ckpts.p, sgi, false, stream)) != EMM_OK) return st;
+        for (int q = 0; q < nq; ++q) {
+            if ((st = copy_state(m, m->ickpts.p, q, true, stream)) != EMM_OK) return st;
+            if (q == nq - 1) break;
+            for (int n = n0 + q * cin; n < n0 + (q + 1) * cin; ++n) {
+                emm::launch_e_step(r, Pe, n, stream);
+                emm::launch_h_step(r, Ph, n, stream);
+            }
+        }
+        for (int q = nq - 1; q >= 0; --q)
+            if ((st = reverse_segment(m->ickpts.p, q, n0 + q * cin, std::min(n0 + (q + 1) * cin, nend))) != EMM_OK)
+                return st;
     }
     // sum over sources, drop the pitch padding, fold the model padding back onto
     // the input cells, and change sign: d/d log sigma = -d/d log(dt/eps)

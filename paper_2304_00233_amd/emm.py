@@ -24,7 +24,8 @@ STATUS = {0: "EMM_OK", -1: "EMM_ERR_ARG", -2: "EMM_ERR_GRID", -3: "EMM_ERR_MODEL
           -4: "EMM_ERR_GEOMETRY", -5: "EMM_ERR_FREQ", -6: "EMM_ERR_CFL",
           -7: "EMM_ERR_NONFINITE", -8: "EMM_ERR_OOM", -9: "EMM_ERR_DEVICE"}
 EXPORTED = ("emm_default_options", "emm_create", "emm_query", "emm_forward",
-            "emm_gradient", "emm_destroy", "emm_status_str", "emm_last_error")
+            "emm_forward_batch", "emm_gradient", "emm_destroy", "emm_status_str",
+            "emm_last_error")
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -43,7 +44,8 @@ class emm_options(C.Structure):
                 ("cpml_R", C.c_double), ("cpml_npow", C.c_double),
                 ("cpml_alpha_max", C.c_double), ("wavelet_fpeak", C.c_double),
                 ("allow_unstable", C.c_int), ("profile", C.c_int), ("tile_kz", C.c_int),
-                ("checkpoint_every", C.c_int), ("graph_steps", C.c_int)]
+                ("checkpoint_every", C.c_int), ("graph_steps", C.c_int),
+                ("checkpoint_inner", C.c_int)]
 
 
 class emm_source(C.Structure):
@@ -55,6 +57,12 @@ class emm_receiver(C.Structure):
     _fields_ = [("x", C.c_double), ("y", C.c_double), ("z", C.c_double)]
 
 
+class emm_job(C.Structure):
+    _fields_ = [("model", C.c_void_p), ("src", C.POINTER(emm_source)), ("nsrc", C.c_int),
+                ("rec", C.POINTER(emm_receiver)), ("nrec", C.c_int), ("chan_mask", C.c_uint),
+                ("freq_hz", _dp), ("nfreq", C.c_int), ("green", _dp)]
+
+
 class emm_info(C.Structure):
     _fields_ = [("dt", C.c_double), ("nt", C.c_int),
                 ("n1pad", C.c_int), ("n2pad", C.c_int), ("n3pad", C.c_int),
@@ -62,7 +70,8 @@ class emm_info(C.Structure):
                 ("e_bytes", C.c_double), ("h_bytes", C.c_double),
                 ("e_kernel_ms", C.c_double), ("h_kernel_ms", C.c_double),
                 ("e_launches", C.c_longlong), ("h_launches", C.c_longlong),
-                ("forward_ms", C.c_double), ("tile_kz", C.c_int)]
+                ("forward_ms", C.c_double), ("tile_kz", C.c_int),
+                ("ckpt_outer", C.c_int), ("ckpt_inner", C.c_int), ("ckpt_bytes", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,6 +92,8 @@ def _load():
                                 C.POINTER(emm_receiver), C.c_int, C.c_uint, _dp, C.c_int,
                                 _dp, C.c_void_p]
     lib.emm_forward.restype = C.c_int
+    lib.emm_forward_batch.argtypes = [C.POINTER(emm_job), C.c_int, C.c_int, C.c_void_p]
+    lib.emm_forward_batch.restype = C.c_int
     lib.emm_gradient.argtypes = [C.c_void_p, C.POINTER(emm_source), C.c_int,
                                  C.POINTER(emm_receiver), C.c_int, C.c_uint, _dp, C.c_int,
                                  _dp, _dp, _dp, _dp, _dp, C.c_void_p]
@@ -209,6 +220,40 @@ def emm_gradient(model, shape, sources, receivers, chan_mask: int, freqs, g_obs=
                              stream), model)
     G = (green[0::2] + 1j * green[1::2]).reshape(ns, nr, nch, nf)
     return grad.reshape(3, n3, n2, n1), G, mis.value
+
+
+def emm_forward_batch(jobs, graph_steps: int = 64, stream=None) -> list:
+    """jobs: sequence of (model handle, sources, receivers, chan_mask, freqs,
+    src_comp or None); all jobs run in one captured hipGraph (see emm.h).
+    Returns one complex128 [nsrc][nrec][nchan][nfreq] array per job."""
+    keep, outs, shapes = [], [], []
+    J = (emm_job * len(jobs))()
+    for j, (h, sources, receivers, chan_mask, freqs, src_comp) in enumerate(jobs):
+        S, ns, R, nr, fr = _acq(sources, receivers, freqs, src_comp, None)
+        nch = bin(chan_mask & 0x3F).count("1")
+        out = np.zeros(2 * max(ns, 1) * max(nr, 1) * max(nch, 1) * max(len(fr), 1))
+        keep += [S, R, fr]
+        outs.append(out)
+        shapes.append((ns, nr, nch, len(fr)))
+        J[j] = emm_job(h, C.cast(S, C.POINTER(emm_source)), ns, C.cast(R, C.POINTER(emm_receiver)),
+                       nr, C.c_uint(chan_mask), fr.ctypes.data_as(_dp), len(fr),
+                       out.ctypes.data_as(_dp))
+    st = _lib.emm_forward_batch(J, len(jobs), graph_steps, stream)
+    if st != 0:
+        # the failing job's model holds the detail
+        detail = ""
+        for h, *_ in jobs:
+            detail = detail or emm_last_error(h)
+        raise EmmError(st, detail)
+    return [(o[0::2] + 1j * o[1::2]).reshape(sh) for o, sh in zip(outs, shapes)]
+
+
+def forward_models(models, graph_steps: int = 64, stream=None) -> list:
+    """Forward of several Model objects (their workloads' acquisitions) in
+    one hipGraph."""
+    jobs = [(m.h, m.w.sources, m.w.receivers, m.w.chan_mask, m.w.freqs, m.w.src_comp)
+            for m in models]
+    return emm_forward_batch(jobs, graph_steps, stream)
 
 
 def emm_destroy(model) -> None:

@@ -35,7 +35,7 @@ def test_exports_every_declared_function(emm):
 
 def test_struct_layout_matches_header(emm, tmp_path):
     src = tmp_path / "layout.c"
-    structs = ["emm_grid", "emm_options", "emm_source", "emm_receiver", "emm_info"]
+    structs = ["emm_grid", "emm_options", "emm_source", "emm_receiver", "emm_info", "emm_job"]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "emm.h"', "int main(void){"]
     for s in structs:
         lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
@@ -58,6 +58,7 @@ def test_default_options(emm):
     o = emm.emm_default_options()
     assert (o.rd, o.nb, o.ne, o.f0, o.cfl, o.nt, o.dft_mode) == (2, 10, -1, 1.0, 0.99, 0, 0)
     assert o.cpml_R == 1e-5 and o.cpml_npow == 2.0 and o.profile == 0
+    assert (o.checkpoint_every, o.checkpoint_inner, o.graph_steps, o.tile_kz) == (0, 0, 0, 0)
 
 
 def test_status_strings(emm):
@@ -117,6 +118,11 @@ def test_null_pointers(emm):
     assert lib.emm_default_options(None) == -1
     assert lib.emm_query(None, None) == -1
     assert lib.emm_forward(None, None, 0, None, 0, 0, None, 0, None, None) == -1
+    assert lib.emm_forward_batch(None, 1, 0, None) == -1
+    jobs = (emm.emm_job * 2)()
+    assert lib.emm_forward_batch(jobs, 0, 0, None) == -1      # no jobs
+    assert lib.emm_forward_batch(jobs, 2, 0, None) == -1      # NULL models
+    assert lib.emm_forward_batch(jobs, 2, -1, None) == -1     # bad graph length
     lib.emm_destroy(None)                           # NULL-safe
 
 

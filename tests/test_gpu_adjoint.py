@@ -59,7 +59,7 @@ def test_gradient_matches_oracle_adjoint(emm, kw):
     _compare(g, g_o, f"{w.name}")
 
 
-def test_checkpoint_interval_and_reuse_are_bitwise(emm):
+def test_checkpoint_schedules_and_reuse_are_bitwise(emm):
     w, wo = _case(seed=36, nt=230)
     G_obs, _ = F.forward(wo)
     with emm.Model(w, checkpoint_every=17) as m:
@@ -68,8 +68,20 @@ def test_checkpoint_interval_and_reuse_are_bitwise(emm):
         g2, _, c2 = m.gradient(g_obs=G_obs)           # and again
     with emm.Model(w, checkpoint_every=40) as m:
         g3, _, c3 = m.gradient(g_obs=G_obs)           # runs its own forward
+    with emm.Model(w, checkpoint_every=40, checkpoint_inner=7) as m:
+        g4, _, c4 = m.gradient(g_obs=G_obs)           # two levels, ragged inner segments
+        inf4 = m.info()
+    with emm.Model(w, checkpoint_every=17, checkpoint_inner=5) as m:
+        m.forward()
+        g5, _, c5 = m.gradient(g_obs=G_obs)           # two levels over reused checkpoints
+    with emm.Model(w) as m:
+        g6, _, c6 = m.gradient(g_obs=G_obs)           # planned schedule
+        inf6 = m.info()
+    assert (inf4["ckpt_outer"], inf4["ckpt_inner"]) == (40, 7)
+    assert inf6["ckpt_outer"] == inf6["ckpt_inner"] > 0 and inf6["ckpt_bytes"] > 0
     assert np.array_equal(g1, g2) and c1 == c2
-    assert np.array_equal(g1, g3) and c1 == c3
+    for g, c in ((g3, c3), (g4, c4), (g5, c5), (g6, c6)):
+        assert np.array_equal(g1, g) and c1 == c
 
 
 def test_cotangent_entry_equals_misfit_entry(emm):

@@ -106,6 +106,32 @@ def test_batched_equals_single_sources(emm):
         assert np.array_equal(Gb[s:s + 1], Gs)
 
 
+def test_multi_model_batch_equals_single_forwards(emm):
+    """Models of uneven sizes, step counts and source counts in one hipGraph
+    (32 steps per block: every job ends with a ragged remainder, and the
+    graph is re-captured as jobs finish) give bitwise the results of their
+    own forwards; the middle job is also held against the oracle."""
+    ws = [configs.small_case(seed=40, shape=(30, 26, 22), nt=150),
+          configs.small_case(seed=41, shape=(37, 29, 23), nt=230, nsrc=2),
+          configs.small_case(seed=42, shape=(24, 22, 20), nt=100, rd=1)]
+    singles = [_run(emm, w)[0] for w in ws]
+    models = [emm.Model(w) for w in ws]
+    try:
+        print("[gpu] forward_models of 3 models", flush=True)
+        outs = emm.forward_models(models, graph_steps=32)
+        infos = [m.info() for m in models]
+    finally:
+        for m in models:
+            m.close()
+    for a, b in zip(outs, singles):
+        assert np.array_equal(a, b)
+    assert [i["nt"] for i in infos] == [150, 230, 100]
+    G_o, _ = F.forward(ws[1])
+    rep = compare(outs[1], G_o, ws[1].channels)
+    print(f"[parity] multi-model job 1: {rep}", flush=True)
+    assert rep["ok"], rep
+
+
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="marine oracle result not generated")
 def test_marine_layered_full_size_vs_stored_oracle(emm):
     g = json.load(open(GOLDEN))
