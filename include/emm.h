@@ -78,7 +78,8 @@ typedef struct {
                               direct steps; with graph_steps, every 8th block of steps runs as
                               direct launches and one pair in 4 of them is timed (emm_query) [0] */
     int    tile_kz;        /* z planes per thread block; 0 = chosen from the grid, -1 = autotuned
-                              on the first forward (timing candidates on this model) [0] */
+                              together with the nontemporal hint on the first forward (timing
+                              candidates on this model) [0] */
     int    checkpoint_every; /* > 0: emm_forward keeps full-state checkpoints every this many
                               steps for a following emm_gradient, and emm_gradient uses this
                               outer interval; 0: emm_gradient plans it (see below) [0] */
@@ -113,6 +114,7 @@ typedef struct {
     int    ckpt_outer;       /* steps between the forward's checkpoints */
     int    ckpt_inner;       /* steps between inner checkpoints (== ckpt_outer: one level) */
     double ckpt_bytes;       /* device bytes of checkpoints and per-step E snapshots */
+    int    nontemporal;      /* 1: the stencil kernels of the last run used nontemporal hints */
 } emm_info;
 
 /* Fill *o with the defaults above. */

@@ -76,7 +76,7 @@ struct emm_model {
     // gradients, transposed tables, injection lists and coefficients
     DevBuf adjf, adjq, adjt, snaps, grad, tabT, inj, injA, adjcpml;
     Acq acq;
-    std::map<int, int> tuned_kz;                    // autotuned z chunk per source count
+    std::map<int, std::pair<int, int>> tuned;       // autotuned (z chunk, stream hint) per source count
     hipEvent_t ev_loop[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ring;       // profiling: start/end pairs
     emm_info info{};
@@ -137,13 +137,25 @@ int choose_kz(const emm_model *m, int xt, int yt, int nsrc) {
     const int nzv = m->np[2] - 2 * m->r;
     if (m->opt.tile_kz > 0) return std::min(m->opt.tile_kz, nzv);
     if (m->opt.tile_kz < 0) {
-        auto it = m->tuned_kz.find(nsrc);
-        if (it != m->tuned_kz.end()) return it->second;
+        auto it = m->tuned.find(nsrc);
+        if (it != m->tuned.end()) return it->second.first;
     }
     const long long per_chunk = (long long)xt * yt * nsrc;
     long long zc = std::max<long long>(1, (4096 + per_chunk - 1) / per_chunk);
     zc = std::min<long long>(zc, std::max(1, nzv / 8));
     return (int)((nzv + zc - 1) / zc);
+}
+
+// Nontemporal hints when the arrays one step touches (fields of all sources
+// and dt/eps) exceed 160 MiB, well inside the 256 MB Infinity Cache below
+// that; the autotuner overrides this with a measurement.
+int choose_stream(const emm_model *m, long long fstride, int nsrc) {
+    if (m->opt.tile_kz < 0) {
+        auto it = m->tuned.find(nsrc);
+        if (it != m->tuned.end()) return it->second.second;
+    }
+    const double resident = (6.0 * nsrc + 3.0) * (double)fstride * sizeof(float);
+    return resident > 160.0 * (1 << 20) ? 1 : 0;
 }
 
 }  // namespace
@@ -586,6 +598,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.zc = (m->np[2] - 2 * r + P.kz - 1) / P.kz;
     P.nsrc = nsrc;
     P.nstencil = P.xt * P.yt * P.zc * nsrc;
+    P.stream = choose_stream(m, fstride, nsrc);
     float *F = (float *)m->fields.p;
     // per-source field arrays are laid out [comp][src][...]: source s at + s * fstride
     P.E1 = F;
@@ -594,6 +607,9 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.H1 = F + (size_t)3 * nsrc * fstride;
     P.H2 = F + (size_t)4 * nsrc * fstride;
     P.H3 = F + (size_t)5 * nsrc * fstride;
+    P.Eo1 = P.E1;
+    P.Eo2 = P.E2;
+    P.Eo3 = P.E3;
     P.ce1 = m->ce[0];
     P.ce2 = m->ce[1];
     P.ce3 = m->ce[2];
@@ -903,6 +919,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     m->info.nt = nt;
     m->info.forward_ms = loop_ms;
     m->info.tile_kz = A.Pe.kz;
+    m->info.nontemporal = A.Pe.stream;
     m->info.e_kernel_ms = prof ? ems : 0.0;
     m->info.h_kernel_ms = prof ? hms : 0.0;
     m->info.e_launches = prof ? nsamp : 0;
@@ -1058,6 +1075,7 @@ emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t
             m->info.nt = m->acq.nt;
             m->info.forward_ms = ms_loop;
             m->info.tile_kz = m->acq.Pe.kz;
+            m->info.nontemporal = m->acq.Pe.stream;
             m->info.e_kernel_ms = m->info.h_kernel_ms = 0.0;
             m->info.e_launches = m->info.h_launches = 0;
         }
@@ -1068,53 +1086,58 @@ emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t
     return st;
 }
 
-// Autotuner of the z chunk per thread block (tile_kz = -1): time a few
-// steps of both stencil kernels for each candidate on this model and
-// acquisition, keep the fastest (cached per source count).  The state it
-// leaves behind is discarded: the time loop starts from zero fields.
+// Autotuner of the z chunk per thread block and of the nontemporal hint
+// (tile_kz = -1): time a few steps of both stencil kernels for each
+// candidate on this model and acquisition, keep the fastest (cached per
+// source count).  The state it leaves behind is discarded: the time loop
+// starts from zero fields.
 emm_status autotune(emm_model *m, hipStream_t stream) {
     Acq &A = m->acq;
-    if (m->opt.tile_kz >= 0 || m->tuned_kz.count(A.nsrc)) return EMM_OK;
+    if (m->opt.tile_kz >= 0 || m->tuned.count(A.nsrc)) return EMM_OK;
     const int nzv = m->np[2] - 2 * m->r;
     std::vector<int> cand = {4, 6, 8, 12, 16, 24, 32, 48, 64, A.Pe.kz};
     hipEvent_t e0, e1;
     HIP_OK(m, hipEventCreate(&e0));
     HIP_OK(m, hipEventCreate(&e1));
     float best = 1e30f;
-    int best_kz = A.Pe.kz;
+    int best_kz = A.Pe.kz, best_st = A.Pe.stream;
     const int steps = 8;
-    for (int kz : cand) {
-        if (kz > nzv) continue;
-        emm::StepParams Pe = A.Pe, Ph = A.Ph;
-        Pe.kz = Ph.kz = kz;
-        Pe.zc = Ph.zc = (nzv + kz - 1) / kz;
-        Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
-        for (int n = 0; n < 2; ++n) {              // warm-up
-            emm::launch_e_step(m->r, Pe, n, stream);
-            emm::launch_h_step(m->r, Ph, n, stream);
+    for (int st : {0, 1})
+        for (int kz : cand) {
+            if (kz > nzv) continue;
+            emm::StepParams Pe = A.Pe, Ph = A.Ph;
+            Pe.kz = Ph.kz = kz;
+            Pe.zc = Ph.zc = (nzv + kz - 1) / kz;
+            Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
+            Pe.stream = Ph.stream = st;
+            for (int n = 0; n < 2; ++n) {              // warm-up
+                emm::launch_e_step(m->r, Pe, n, stream);
+                emm::launch_h_step(m->r, Ph, n, stream);
+            }
+            HIP_OK(m, hipEventRecord(e0, stream));
+            for (int n = 0; n < steps; ++n) {
+                emm::launch_e_step(m->r, Pe, n, stream);
+                emm::launch_h_step(m->r, Ph, n, stream);
+            }
+            HIP_OK(m, hipEventRecord(e1, stream));
+            HIP_OK(m, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(m, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_kz = kz;
+                best_st = st;
+            }
         }
-        HIP_OK(m, hipEventRecord(e0, stream));
-        for (int n = 0; n < steps; ++n) {
-            emm::launch_e_step(m->r, Pe, n, stream);
-            emm::launch_h_step(m->r, Ph, n, stream);
-        }
-        HIP_OK(m, hipEventRecord(e1, stream));
-        HIP_OK(m, hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_OK(m, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            best_kz = kz;
-        }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_OK(m, hipGetLastError());
-    m->tuned_kz[A.nsrc] = best_kz;
+    m->tuned[A.nsrc] = {best_kz, best_st};
     for (emm::StepParams *P : {&A.Pe, &A.Ph}) {
         P->kz = best_kz;
         P->zc = (nzv + best_kz - 1) / best_kz;
         P->nstencil = P->xt * P->yt * P->zc * A.nsrc;
+        P->stream = best_st;
     }
     return EMM_OK;
 }
@@ -1473,16 +1496,24 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     float *snap = (float *)m->snaps.p;
     const size_t snap_bytes = (size_t)3 * nsrc * fstride * sizeof(float);
     // one segment [n0, nend) from checkpoint c of buffer `base`: recompute it
-    // keeping E after every step, then reverse its steps
+    // with the E step writing out of place into the next snapshot slot (so E
+    // after every step is kept without copies), then reverse its steps
     auto reverse_segment = [&](void *base, int c, int n0, int nend) -> emm_status {
         emm_status s2;
         if ((s2 = copy_state(m, base, c, false, stream)) != EMM_OK) return s2;
         HIP_OK(m, hipMemcpyAsync(snap, m->fields.p, snap_bytes, hipMemcpyDeviceToDevice, stream));
+        const size_t cs = (size_t)nsrc * fstride;               // component stride
         for (int n = n0; n < nend; ++n) {
-            emm::launch_e_step(r, Pe, n, stream);
-            emm::launch_h_step(r, Ph, n, stream);
-            HIP_OK(m, hipMemcpyAsync(snap + (size_t)(n - n0 + 1) * 3 * nsrc * fstride, m->fields.p, snap_bytes,
-                                     hipMemcpyDeviceToDevice, stream));
+            float *Ein = snap + (size_t)(n - n0) * 3 * cs, *Eout = snap + (size_t)(n - n0 + 1) * 3 * cs;
+            emm::StepParams Pr = Pe, Qr = Ph;
+            Pr.E1 = Ein;
+            Pr.E2 = Ein + cs;
+            Pr.E3 = Ein + 2 * cs;
+            Pr.Eo1 = Qr.E1 = Qr.Eo1 = Eout;
+            Pr.Eo2 = Qr.E2 = Qr.Eo2 = Eout + cs;
+            Pr.Eo3 = Qr.E3 = Qr.Eo3 = Eout + 2 * cs;
+            emm::launch_e_step(r, Pr, n, stream);
+            emm::launch_h_step(r, Qr, n, stream);
         }
         for (int n = nend - 1; n >= n0; --n) {
             if (nb) emm::launch_adj_filter(true, PE, stream);

@@ -24,8 +24,10 @@ struct StepParams {
     int nsrc;
     int nstencil;               // xt * yt * zc * nsrc
     int nrecblk;                // receiver blocks placed first (multiple of 8)
+    int stream;                 // 1: nontemporal loads/stores of the arrays touched once per launch
     // fields (source 0; source s at + s * fstride)
     float *E1, *E2, *E3, *H1, *H2, *H3;
+    float *Eo1, *Eo2, *Eo3;          // where the E step writes E (== E1..3: in place)
     const float *ce1, *ce2, *ce3;   // dt/eps at Ex/Ey/Ez positions
     float ch;                        // dt/mu0
     // FD tables [n_d][2R]: cm = D- at integer nodes, cp = D+ at half nodes

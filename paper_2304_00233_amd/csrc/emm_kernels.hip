@@ -13,6 +13,12 @@
 // H step).  No curl arrays are written (the paper's curl and update kernels
 // are one pass here).
 //
+// Arrays that a launch touches once (the updated field, dt/eps) can be
+// moved with nontemporal hints (p.stream): on grids whose working set is
+// larger than the Infinity Cache this keeps the cache for the re-read halo
+// planes; on smaller grids plain accesses let the arrays stay resident
+// between steps.  The autotuner times both.
+//
 // Work decomposition: a 256-thread block covers a 64 (x) by 4 (y) tile of
 // columns and marches a chunk of z planes.  Each wavefront owns one 64-wide
 // row along x (coalesced 256-byte accesses).  Per plane, the x/y stencil
@@ -28,6 +34,17 @@ constexpr int TY = kTileY;
 constexpr int NT = kTileX * TY;
 
 int block_threads() { return NT; }
+
+template <bool ST>
+__device__ __forceinline__ float ld1(const float *p) {
+    if constexpr (ST) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool ST>
+__device__ __forceinline__ void st1(float *p, float v) {
+    if constexpr (ST) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 // Hardware dispatches workgroup w to XCD w % 8; give every XCD one
 // contiguous range of logical tiles.
@@ -83,6 +100,7 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
     }
 }
 
+// ST: nontemporal hints on the updated field and dt/eps.
 // HS = false: E step (reads H, updates E, D- tables, integer-node CPML,
 //             injects J, records H channels);
 // HS = true:  H step (reads E, updates H, D+ tables, half-node CPML,
@@ -95,7 +113,7 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
 // loads are in flight.  Two LDS buffers make one barrier per plane enough: a
 // buffer is rewritten only after every wave has passed the barrier that
 // follows its last use.
-template <int R, bool HS>
+template <int R, bool HS, bool ST>
 __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg) {
     const int n = (p.step_base ? *p.step_base : 0) + n_arg;
     constexpr int L = 2 * R;
@@ -140,9 +158,12 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     A2 += fo;
     A3 += fo;
     const int plane = (int)p.plane;                   // 32-bit offsets below this base
-    float *U1 = (HS ? p.H1 : p.E1) + fo;
-    float *U2 = (HS ? p.H2 : p.E2) + fo;
-    float *U3 = (HS ? p.H3 : p.E3) + fo;
+    const float *U1 = (HS ? p.H1 : p.E1) + fo;
+    const float *U2 = (HS ? p.H2 : p.E2) + fo;
+    const float *U3 = (HS ? p.H3 : p.E3) + fo;
+    float *O1 = (HS ? p.H1 : p.Eo1) + fo;     // updated field (E may go out of place)
+    float *O2 = (HS ? p.H2 : p.Eo2) + fo;
+    float *O3 = (HS ? p.H3 : p.Eo3) + fo;
 
     const float *tx_ = HS ? p.cpx : p.cmx;
     const float *ty_ = HS ? p.cpy : p.cmy;
@@ -248,13 +269,13 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         e2n = A2[ge];
         if (valid) {
             const unsigned g = (unsigned)(pk + own);
-            un1 = U1[g];
-            un2 = U2[g];
-            un3 = U3[g];
+            un1 = ld1<ST>(&U1[g]);
+            un2 = ld1<ST>(&U2[g]);
+            un3 = ld1<ST>(&U3[g]);
             if (!HS) {
-                cn1 = ce1[g];
-                cn2 = ce2[g];
-                cn3 = ce3[g];
+                cn1 = ld1<ST>(&ce1[g]);
+                cn2 = ld1<ST>(&ce2[g]);
+                cn3 = ld1<ST>(&ce3[g]);
             }
         }
     };
@@ -323,9 +344,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
             float c1 = d2a3 - d3a2, c2 = d3a1 - d1a3, c3 = d1a2 - d2a1;
             const unsigned g = (unsigned)(k * plane + own);
             if (HS) {
-                U1[g] = u1 - p.ch * c1;
-                U2[g] = u2 - p.ch * c2;
-                U3[g] = u3 - p.ch * c3;
+                st1<ST>(&O1[g], u1 - p.ch * c1);
+                st1<ST>(&O2[g], u2 - p.ch * c2);
+                st1<ST>(&O3[g], u3 - p.ch * c3);
             } else {
                 if (k >= sbz && k < sbz + L && j >= sby && j < sby + L && i >= sbx && i < sbx + L) {
                     const float jv = sn * sq[((k - sbz) * L + (j - sby)) * L + (i - sbx)];
@@ -333,9 +354,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
                     else if (scomp == 1) c2 -= jv;
                     else c3 -= jv;
                 }
-                U1[g] = u1 + ce1 * c1;
-                U2[g] = u2 + ce2 * c2;
-                U3[g] = u3 + ce3 * c3;
+                st1<ST>(&O1[g], u1 + ce1 * c1);
+                st1<ST>(&O2[g], u2 + ce2 * c2);
+                st1<ST>(&O3[g], u3 + ce3 * c3);
             }
         }
 #pragma unroll
@@ -346,18 +367,21 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     }
 }
 
-template <bool HS>
+template <bool HS, bool ST>
 static void launch(int r, const StepParams &p, int n, hipStream_t s) {
     const dim3 grid(p.nrecblk + p.nstencil), block(NT);
     switch (r) {
-    case 1: hipLaunchKernelGGL((step_kernel<1, HS>), grid, block, 0, s, p, n); break;
-    case 2: hipLaunchKernelGGL((step_kernel<2, HS>), grid, block, 0, s, p, n); break;
-    case 3: hipLaunchKernelGGL((step_kernel<3, HS>), grid, block, 0, s, p, n); break;
-    default: hipLaunchKernelGGL((step_kernel<4, HS>), grid, block, 0, s, p, n); break;
+    case 1: hipLaunchKernelGGL((step_kernel<1, HS, ST>), grid, block, 0, s, p, n); break;
+    case 2: hipLaunchKernelGGL((step_kernel<2, HS, ST>), grid, block, 0, s, p, n); break;
+    case 3: hipLaunchKernelGGL((step_kernel<3, HS, ST>), grid, block, 0, s, p, n); break;
+    default: hipLaunchKernelGGL((step_kernel<4, HS, ST>), grid, block, 0, s, p, n); break;
     }
 }
 
-void launch_e_step(int r, const StepParams &p, int n, hipStream_t s) { launch<false>(r, p, n, s); }
+void launch_e_step(int r, const StepParams &p, int n, hipStream_t s) {
+    if (p.stream) launch<false, true>(r, p, n, s);
+    else launch<false, false>(r, p, n, s);
+}
 
 // graph replays: advance the device step counter by k after each replay
 __global__ void advance_kernel(int *step, int k) {
@@ -367,6 +391,9 @@ __global__ void advance_kernel(int *step, int k) {
 void launch_advance(int *step, int k, hipStream_t s) {
     hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, step, k);
 }
-void launch_h_step(int r, const StepParams &p, int n, hipStream_t s) { launch<true>(r, p, n, s); }
+void launch_h_step(int r, const StepParams &p, int n, hipStream_t s) {
+    if (p.stream) launch<true, true>(r, p, n, s);
+    else launch<true, false>(r, p, n, s);
+}
 
 }  // namespace emm

@@ -71,7 +71,8 @@ class emm_info(C.Structure):
                 ("e_kernel_ms", C.c_double), ("h_kernel_ms", C.c_double),
                 ("e_launches", C.c_longlong), ("h_launches", C.c_longlong),
                 ("forward_ms", C.c_double), ("tile_kz", C.c_int),
-                ("ckpt_outer", C.c_int), ("ckpt_inner", C.c_int), ("ckpt_bytes", C.c_double)]
+                ("ckpt_outer", C.c_int), ("ckpt_inner", C.c_int), ("ckpt_bytes", C.c_double),
+                ("nontemporal", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
