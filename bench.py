@@ -87,6 +87,70 @@ def batched_comparison(emm, w, nsrc: int, group: int, ckpt: int):
     return out
 
 
+def multi_model_comparison(emm, graph: int):
+    """Eight seeded layered + box models from 64^3 to 160 x 160 x 120 nodes
+    (each with its own dt and step count): their forwards one after another
+    versus all of them as branches of one hipGraph (emm_forward_batch)."""
+    import numpy as np
+    from workloads import configs
+    ws = configs.batched_models()
+    models = [emm.Model(w, tile_kz=-1, graph_steps=graph) for w in ws]
+    try:
+        for m in models:                                       # tune + warm
+            m.forward()
+        t = time.perf_counter()
+        seq = [m.forward() for m in models]
+        t_seq = time.perf_counter() - t
+        emm.forward_models(models, graph_steps=graph)          # warm
+        t = time.perf_counter()
+        bat = emm.forward_models(models, graph_steps=graph)
+        t_bat = time.perf_counter() - t
+        cellsteps = sum(m.info()["cells"] * m.info()["nt"] for m in models)
+    finally:
+        for m in models:
+            m.close()
+    same = all(np.array_equal(a, b) for a, b in zip(seq, bat))
+    return {"models": [w.name for w in ws], "sequential_s": t_seq, "one_graph_s": t_bat,
+            "speedup": t_seq / t_bat, "gcell_steps": cellsteps / 1e9,
+            "one_graph_gcell_step_per_s": cellsteps / t_bat / 1e9, "bitwise_equal": same}
+
+
+def large_fwd_grad(emm, nt: int, group: int, graph: int):
+    """The 400 x 400 x 200 marine grid at 8th order (438 x 438 x 238 padded
+    cells), 8 x-dipoles, 400 receivers, 5 frequencies, compensated FP32 DTFT:
+    plain loop of one-source forwards, one batched forward of the 8
+    sources, and forward + gradient (log misfit against the batched result
+    scaled by 1.01) in groups of `group` sources, each under the planned
+    checkpoint schedule."""
+    from workloads import configs
+    w = configs.large_marine(nt=nt, rd=4, nsrc=8)
+    out = {"workload": w.name, "time_steps": nt, "sources": 8, "gradient_group": group}
+    with emm.Model(w, tile_kz=-1, graph_steps=graph) as m:
+        m.forward(sources=w.sources[:1], src_comp=w.src_comp[:1])         # tune + warm
+        t = time.perf_counter()
+        for s in range(8):
+            m.forward(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1])
+        out["plain_forward_loop_s"] = time.perf_counter() - t
+        m.forward()                                                     # tune for 8 + warm
+        t = time.perf_counter()
+        Gb = m.forward()
+        out["batched_forward_s"] = time.perf_counter() - t
+        G_obs = Gb * 1.01
+        sched = []
+        t = time.perf_counter()
+        for g0 in range(0, 8, group):
+            sl = slice(g0, min(8, g0 + group))
+            m.gradient(g_obs=G_obs[sl], sources=w.sources[sl], src_comp=w.src_comp[sl])
+            i = m.info()
+            sched.append([i["ckpt_outer"], i["ckpt_inner"], i["ckpt_bytes"] / 2 ** 30])
+        out["forward_gradient_s"] = time.perf_counter() - t
+        out["checkpoint_schedule_outer_inner_GiB"] = sched
+        out["cells"] = m.info()["cells"]
+    out["batched_forward_vs_plain_loop"] = out["plain_forward_loop_s"] / out["batched_forward_s"]
+    out["forward_gradient_over_plain_forward_loop"] = out["forward_gradient_s"] / out["plain_forward_loop_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +170,13 @@ def main():
                     help="sources of the batched comparison (0: skip)")
     ap.add_argument("--grad-group", type=int, default=8)
     ap.add_argument("--grad-ckpt", type=int, default=128)
+    ap.add_argument("--multi-model", action="store_true",
+                    help="also time 8 models of uneven sizes in one hipGraph vs one after another")
+    ap.add_argument("--large-fwd-grad", type=int, default=0, metavar="NT",
+                    help="also time the 8-source 8th-order forward + gradient on the 400x400x200 "
+                         "grid with NT time steps (0: skip)")
+    ap.add_argument("--large-group", type=int, default=2,
+                    help="sources per emm_gradient call of --large-fwd-grad")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -195,6 +266,15 @@ def main():
         log(f"[bench] batched comparison with {args.batched} sources")
         out["batched"] = batched_comparison(emm, w, args.batched, args.grad_group, args.grad_ckpt)
         log(f"[bench] batched: {out['batched']}")
+    if args.multi_model:
+        log("[bench] multi-model comparison")
+        out["multi_model"] = multi_model_comparison(emm, args.graph or 64)
+        log(f"[bench] multi-model: {out['multi_model']}")
+    if args.large_fwd_grad:
+        log(f"[bench] large 8-source forward + gradient, {args.large_fwd_grad} steps")
+        out["large_fwd_grad"] = large_fwd_grad(emm, args.large_fwd_grad, args.large_group,
+                                               args.graph or 64)
+        log(f"[bench] large: {out['large_fwd_grad']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

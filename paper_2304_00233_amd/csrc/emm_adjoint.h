@@ -3,10 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include "emm_internal.h"
+
 namespace emm {
 
 struct AdjParams {
     int n1, n2, n3, pitch, r, nb, nsrc;
+    int kz;                       // z planes per thread block of the gathers
+    int xt, yt, zc, nstencil;     // tiles along x, y, z chunks; xt * yt * zc * nsrc
     long long fstride;            // one source's field array (plane * n3)
     // inputs (filtered by the CPML reverse) and outputs of the gather,
     // source 0 (source s at + s * fstride)
@@ -24,9 +28,11 @@ struct AdjParams {
     float *T[6];
     long long sxs, sys, szs;      // per-source strides of the x, y, z slab arrays
     // gradient (reverse of the E update only): E^{n+1}, E^n snapshots laid
-    // out like the fields ([comp][src][...]), per-source accumulators
-    // grad[src][comp][...] (double)
+    // out like the fields ([comp][src][...]); per-source partial sums
+    // grad32[src][comp][...] of Et (E^{n+1} - E^n) over a few steps, flushed
+    // into grad[src][comp][...] (double) divided by dt/eps
     const float *E_next, *E_prev;
+    float *grad32;
     double *grad;
     long long gstride;            // component stride of one source's grad (fstride)
 };
@@ -47,7 +53,8 @@ struct InjectParams {
 };
 
 void launch_adj_filter(bool rev_h, const AdjParams &p, hipStream_t st);
-void launch_adj_gather(int r, bool rev_h, const AdjParams &p, hipStream_t st);
 void launch_adj_inject(const InjectParams &p, int n, hipStream_t st);
+void launch_adj_flush(const AdjParams &p, hipStream_t st);
+void launch_adj_tile(int r, bool rev_h, const AdjParams &p, hipStream_t st);
 
 }  // namespace emm

@@ -6,7 +6,9 @@
 //   1. reverse of the H update: Et += (dt/eps) dt/mu0 curlT(F(Hb)), with
 //      the transposed D+ tables (their stencil has the D- shape);
 //   2. receiver sources of the E channels (stamp (n+1) dt);
-//   3. reverse of the E update: grad += Ebar (E^{n+1} - E^n) and
+//   3. reverse of the E update: grad += Ebar (E^{n+1} - E^n) (summed as
+//      Et (E^{n+1} - E^n) in FP32 over a few steps, then divided by dt/eps
+//      and added to the FP64 gradient) and
 //      Hb -= curlT(F(Et)), with the transposed D- tables (D+ shape);
 //   4. receiver sources of the H channels (stamp (n+1/2) dt).
 // The curl structure is the forward one (component 1 has y and z taps,
@@ -22,11 +24,6 @@
 namespace emm {
 
 constexpr int AT = 256;
-
-// slab index of position i on an axis of n nodes, or -1 outside the slabs
-__device__ __forceinline__ int slab_index(int i, int n, int nb) {
-    return i < nb ? i : (i > n - 1 - nb ? i - (n - 2 * nb) : -1);
-}
 
 // 1. CPML reverse filter on the slab cells of the update set, for the six
 // (input component, tap axis) pairs.  One thread per slab cell of one axis.
@@ -105,81 +102,190 @@ __global__ __launch_bounds__(AT) void adj_filter(const AdjParams p) {
     T1[id] = v1 + a * ps1;
 }
 
-// value of the CPML-filtered input `comp` (0..2) at a tap position that
-// differs from an update-set cell only along `axis`; 0 outside the update set
-template <int AXIS>
-__device__ __forceinline__ float tap(const AdjParams &p, const float *in, int comp, int s,
-                                     int k, int j, int i, long long g) {
-    const int r = p.r, nb = p.nb, nb2 = 2 * p.nb;
-    const int q = AXIS == 0 ? i : (AXIS == 1 ? j : k);
-    const int n = AXIS == 0 ? p.n1 : (AXIS == 1 ? p.n2 : p.n3);
-    if (q < r || q > n - 1 - r) return 0.f;
-    const int si = slab_index(q, n, nb);
-    if (si < 0) return in[g];
-    // slab slot of this (comp, axis): x: comps 1,2; y: comps 0,2; z: comps 0,1
-    const int slot = AXIS == 0 ? (comp == 1 ? 0 : 1) : (AXIS == 1 ? (comp == 0 ? 0 : 1) : (comp == 0 ? 0 : 1));
-    const float *T = p.T[2 * AXIS + slot];
-    long long id;
-    if (AXIS == 0) id = ((long long)k * p.n2 + j) * nb2 + si + (long long)s * p.sxs;
-    else if (AXIS == 1) id = ((long long)k * nb2 + si) * p.pitch + i + (long long)s * p.sys;
-    else id = ((long long)si * p.n2 + j) * p.pitch + i + (long long)s * p.szs;
-    return T[id];
-}
-
-// 2./3. transposed curl gathers.  One thread per (i, j) column of one
-// source, looping over z.  REV_H = true: Et += (dt/eps) dtmu curlT(F(Hb))
-// with transposed D+ tables (offsets -R..R-1); REV_H = false: gradient,
-// then Hb -= scale curlT(F(Et)) (scale 1) with transposed D- tables
-// (offsets -R+1..R).
+// 2./3. transposed curl gathers, in the layout of the forward stencil
+// kernel: a 64 x 4 tile of columns per 256-thread block marching a
+// chunk of kz planes, x/y taps staged in LDS per plane (double-buffered,
+// one barrier per plane, the next plane's loads issued right after it),
+// z taps in a 2r-deep register queue.  Because the CPML reverse filter
+// makes the tap value depend on the tap axis inside a slab, the staged
+// copies are per (component, axis): the x taps of components 2 and 3 over
+// the own rows with the x halo, the y taps of components 1 and 3 over the
+// own columns with the y halo; every staged value is the filtered one (the
+// slab array T inside the slab of its axis, the field elsewhere, zero off
+// the update set on that axis).
 template <int R, bool REV_H>
-__global__ __launch_bounds__(AT) void adj_gather(const AdjParams p) {
+__global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
+    constexpr int TY = kTileY, NT = kTileX * kTileY;
     constexpr int L = 2 * R;
-    constexpr int LO = REV_H ? R : R - 1;      // taps at q - LO .. q - LO + L - 1
-    const long long t = (long long)blockIdx.x * AT + threadIdx.x;
-    const long long ncol = (long long)p.n2 * p.pitch;
-    if (t >= ncol * p.nsrc) return;
-    const int s = (int)(t / ncol);
-    const long long c = t - (long long)s * ncol;
-    const int j = (int)(c / p.pitch), i = (int)(c - (long long)j * p.pitch);
-    if (i < R || i > p.n1 - 1 - R || j < R || j > p.n2 - 1 - R) return;
+    constexpr int HL = REV_H ? R : R - 1;     // taps at q - HL .. q - HL + L - 1
+    constexpr int W = kTileX + L - 1;
+    constexpr int HR = TY + L - 1;
+    constexpr int NX = (TY * W + NT - 1) / NT;        // x-type staging loads per thread
+    constexpr int NY = (HR * kTileX + NT - 1) / NT;   // y-type staging loads per thread
+    __shared__ float s3x[2][TY][W], s2x[2][TY][W];    // x taps of components 3 and 2
+    __shared__ float s3y[2][HR][kTileX], s1y[2][HR][kTileX];   // y taps of components 3 and 1
+
+    int t = xcd_tile(blockIdx.x, p.nstencil);
+    const int s = t % p.nsrc;
+    t /= p.nsrc;
+    const int bxt = t % p.xt;
+    t /= p.xt;
+    const int byt = t % p.yt;
+    const int bzt = t / p.yt;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int i0 = bxt * kTileX, j0 = R + byt * TY;
+    const int i = i0 + tx, j = j0 + ty;
+    const int k0 = R + bzt * p.kz, k1 = min(k0 + p.kz, p.n3 - R);
+    const bool valid = i >= R && i <= p.n1 - 1 - R && j <= p.n2 - 1 - R;
+    const int jc = min(j, p.n2 - 1);
+    const int nb = p.nb, nb2 = 2 * p.nb;
+    const int plane = p.n2 * p.pitch;
     const long long fo = (long long)s * p.fstride;
-    const float *in[3] = {p.in1 + fo, p.in2 + fo, p.in3 + fo};
-    float *out1 = p.out1 + fo, *out2 = p.out2 + fo, *out3 = p.out3 + fo;
-    const float *tx_ = p.tx + i * L, *ty_ = p.ty + j * L;
-    const long long plane = (long long)p.n2 * p.pitch;
-    for (int k = R; k <= p.n3 - 1 - R; ++k) {
-        const long long g = k * plane + (long long)j * p.pitch + i;
-        const float *tz_ = p.tz + k * L;
-        // the six transposed derivatives of the filtered inputs
-        float dx1 = 0.f, dx2 = 0.f, dy0 = 0.f, dy2 = 0.f, dz0 = 0.f, dz1 = 0.f;
+    const float *A1 = p.in1 + fo, *A2 = p.in2 + fo, *A3 = p.in3 + fo;
+    // slab arrays of this source: x [n3][n2][2nb], y [n3][2nb][pitch], z [2nb][n2][pitch]
+    const float *Tx2 = p.T[0] + s * p.sxs, *Tx3 = p.T[1] + s * p.sxs;
+    const float *Ty1 = p.T[2] + s * p.sys, *Ty3 = p.T[3] + s * p.sys;
+    const float *Tz1 = p.T[4] + s * p.szs, *Tz2 = p.T[5] + s * p.szs;
+    const int xplane = p.n2 * nb2, yplane = nb2 * p.pitch;
+
+    const int ic = valid ? i : R;
+    float cx[L], cy[L];
 #pragma unroll
-        for (int m = 0; m < L; ++m) {
-            const int o = m - LO;
-            dx1 += tx_[m] * tap<0>(p, in[1], 1, s, k, j, i + o, g + o);
-            dx2 += tx_[m] * tap<0>(p, in[2], 2, s, k, j, i + o, g + o);
-            dy0 += ty_[m] * tap<1>(p, in[0], 0, s, k, j + o, i, g + (long long)o * p.pitch);
-            dy2 += ty_[m] * tap<1>(p, in[2], 2, s, k, j + o, i, g + (long long)o * p.pitch);
-            dz0 += tz_[m] * tap<2>(p, in[0], 0, s, k + o, j, i, g + o * plane);
-            dz1 += tz_[m] * tap<2>(p, in[1], 1, s, k + o, j, i, g + o * plane);
+    for (int m = 0; m < L; ++m) {
+        cx[m] = p.tx[ic * L + m];
+        cy[m] = p.ty[jc * L + m];
+    }
+    auto slab = [&](int q, int n) { return q < nb ? q : (q > n - 1 - nb ? q - (n - nb2) : -1); };
+    auto on_set = [&](int q, int n) { return q >= R && q <= n - 1 - R; };
+
+    // x-type element u: own row ly, column i0 - HL + lx.  Per element: field
+    // offset in the plane (or -1: zero), x-slab offset in the plane (or -1).
+    int xo[NX], xs[NX];
+#pragma unroll
+    for (int u = 0; u < NX; ++u) {
+        const int e = tid + u * NT;
+        const int ly = e / W, lx = e - ly * W;
+        const int gj = j0 + ly, gi = i0 - HL + lx;
+        const bool in = e < TY * W && gj < p.n2 && gi >= 0 && gi < p.n1 && on_set(gi, p.n1);
+        const int si = in ? slab(gi, p.n1) : -1;
+        xo[u] = in ? gj * p.pitch + gi : -1;
+        xs[u] = si >= 0 ? gj * nb2 + si : -1;
+    }
+    // y-type element u: row j0 - HL + ly, own column
+    int yo[NY], ys[NY];
+#pragma unroll
+    for (int u = 0; u < NY; ++u) {
+        const int e = tid + u * NT;
+        const int ly = e >> 6, lx = e & 63;
+        const int gj = j0 - HL + ly, gi = i0 + lx;
+        const bool in = e < HR * kTileX && gj >= 0 && gj < p.n2 && on_set(gj, p.n2) && gi < p.pitch;
+        const int si = in ? slab(gj, p.n2) : -1;
+        yo[u] = in ? gj * p.pitch + gi : -1;
+        ys[u] = si >= 0 ? si * p.pitch + gi : -1;
+    }
+    const int own = jc * p.pitch + i;
+    const int ownz = jc * p.pitch + i;               // offset inside a z-slab plane
+    // z-filtered value of component (1: A1/Tz1, 2: A2/Tz2) at plane kk of the own column
+    auto zval = [&](const float *A, const float *Tz, int kk) -> float {
+        if (kk < R || kk > p.n3 - 1 - R) return 0.f;
+        const int sk = slab(kk, p.n3);
+        return sk >= 0 ? Tz[(unsigned)(sk * plane + ownz)] : A[(unsigned)(kk * plane + own)];
+    };
+    float q1[L], q2[L];
+#pragma unroll
+    for (int m = 0; m < L - 1; ++m) {
+        q1[m] = zval(A1, Tz1, k0 - HL + m);
+        q2[m] = zval(A2, Tz2, k0 - HL + m);
+    }
+    float *O1 = p.out1 + fo, *O2 = p.out2 + fo, *O3 = p.out3 + fo;
+    const long long fs3 = (long long)p.nsrc * p.fstride;     // component stride of E snapshots
+    const float *En1 = REV_H ? nullptr : p.E_next + fo, *En = REV_H ? nullptr : p.E_prev + fo;
+    float *gr = REV_H ? nullptr : p.grad32 + (long long)s * 3 * p.gstride;
+
+    float f3x[NX], f2x[NX], f3y[NY], f1y[NY], e1n = 0.f, e2n = 0.f;
+    float o1 = 0.f, o2 = 0.f, o3 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
+    auto issue = [&](int k) {
+        const int pk = k * plane;
+#pragma unroll
+        for (int u = 0; u < NX; ++u) {
+            f3x[u] = xs[u] >= 0 ? Tx3[(unsigned)(k * xplane + xs[u])] : (xo[u] >= 0 ? A3[(unsigned)(pk + xo[u])] : 0.f);
+            f2x[u] = xs[u] >= 0 ? Tx2[(unsigned)(k * xplane + xs[u])] : (xo[u] >= 0 ? A2[(unsigned)(pk + xo[u])] : 0.f);
         }
-        // forward curl signs: out1 = D2(c3) - D3(c2), out2 = D3(c1) - D1(c3), out3 = D1(c2) - D2(c1)
-        const float c1 = dy2 - dz1, c2 = dz0 - dx2, c3 = dx1 - dy0;
-        if (REV_H) {
-            out1[g] += p.ce1[g] * p.scale * c1;
-            out2[g] += p.ce2[g] * p.scale * c2;
-            out3[g] += p.ce3[g] * p.scale * c3;
-        } else {
-            // gradient wrt log(dt/eps): Ebar (E^{n+1} - E^n), Ebar = Et / (dt/eps)
-            const float *En1 = p.E_next + fo, *En = p.E_prev + fo;
-            const long long fs3 = (long long)p.nsrc * p.fstride;   // component stride of E snapshots
-            double *gr = p.grad + (long long)s * 3 * p.gstride;
-            gr[g] += (double)(in[0][g] / p.ce1[g]) * (double)(En1[g] - En[g]);
-            gr[g + p.gstride] += (double)(in[1][g] / p.ce2[g]) * (double)(En1[g + fs3] - En[g + fs3]);
-            gr[g + 2 * p.gstride] += (double)(in[2][g] / p.ce3[g]) * (double)(En1[g + 2 * fs3] - En[g + 2 * fs3]);
-            // Hbar update has the signs of the forward H step
-            out1[g] -= p.scale * c1;
-            out2[g] -= p.scale * c2;
-            out3[g] -= p.scale * c3;
+#pragma unroll
+        for (int u = 0; u < NY; ++u) {
+            f3y[u] = ys[u] >= 0 ? Ty3[(unsigned)(k * yplane + ys[u])] : (yo[u] >= 0 ? A3[(unsigned)(pk + yo[u])] : 0.f);
+            f1y[u] = ys[u] >= 0 ? Ty1[(unsigned)(k * yplane + ys[u])] : (yo[u] >= 0 ? A1[(unsigned)(pk + yo[u])] : 0.f);
+        }
+        e1n = zval(A1, Tz1, k - HL + L - 1);
+        e2n = zval(A2, Tz2, k - HL + L - 1);
+        if (valid) {
+            const unsigned g = (unsigned)(pk + own);
+            o1 = O1[g];
+            o2 = O2[g];
+            o3 = O3[g];
+            if (REV_H) {
+                w1 = p.ce1[g];
+                w2 = p.ce2[g];
+                w3 = p.ce3[g];
+            } else {
+                // raw Et at the own cell times E^{n+1} - E^n
+                w1 = A1[g] * (En1[g] - En[g]);
+                w2 = A2[g] * (En1[g + fs3] - En[g + fs3]);
+                w3 = A3[g] * (En1[g + 2 * fs3] - En[g + 2 * fs3]);
+            }
+        }
+    };
+    issue(k0);
+    for (int k = k0; k < k1; ++k) {
+        const int b = (k - k0) & 1;
+        q1[L - 1] = e1n;
+        q2[L - 1] = e2n;
+#pragma unroll
+        for (int u = 0; u < NX; ++u)
+            if (u < NX - 1 || tid + u * NT < TY * W) {
+                (&s3x[b][0][0])[tid + u * NT] = f3x[u];
+                (&s2x[b][0][0])[tid + u * NT] = f2x[u];
+            }
+#pragma unroll
+        for (int u = 0; u < NY; ++u)
+            if (u < NY - 1 || tid + u * NT < HR * kTileX) {
+                (&s3y[b][0][0])[tid + u * NT] = f3y[u];
+                (&s1y[b][0][0])[tid + u * NT] = f1y[u];
+            }
+        const float u1 = o1, u2 = o2, u3 = o3, v1 = w1, v2 = w2, v3 = w3;
+        __syncthreads();
+        if (k + 1 < k1) issue(k + 1);
+        if (valid) {
+            const float *cz = p.tz + k * L;
+            float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
+#pragma unroll
+            for (int m = 0; m < L; ++m) {
+                d2a3 += cy[m] * s3y[b][ty + m][tx];
+                d2a1 += cy[m] * s1y[b][ty + m][tx];
+                d1a3 += cx[m] * s3x[b][ty][tx + m];
+                d1a2 += cx[m] * s2x[b][ty][tx + m];
+                d3a2 += cz[m] * q2[m];
+                d3a1 += cz[m] * q1[m];
+            }
+            const float c1 = d2a3 - d3a2, c2 = d3a1 - d1a3, c3 = d1a2 - d2a1;
+            const unsigned g = (unsigned)(k * plane + own);
+            if (REV_H) {
+                O1[g] = u1 + v1 * p.scale * c1;
+                O2[g] = u2 + v2 * p.scale * c2;
+                O3[g] = u3 + v3 * p.scale * c3;
+            } else {
+                gr[g] += v1;
+                gr[g + p.gstride] += v2;
+                gr[g + 2 * p.gstride] += v3;
+                O1[g] = u1 - p.scale * c1;
+                O2[g] = u2 - p.scale * c2;
+                O3[g] = u3 - p.scale * c3;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < L - 1; ++m) {
+            q1[m] = q1[m + 1];
+            q2[m] = q2[m + 1];
         }
     }
 }
@@ -209,6 +315,28 @@ __global__ __launch_bounds__(AT) void adj_inject(const InjectParams p, int n) {
     F[g] += scale * acc;
 }
 
+// grad += grad32 / (dt/eps), grad32 = 0, over every cell of every source
+__global__ __launch_bounds__(AT) void adj_flush(const AdjParams p) {
+    const long long t = (long long)blockIdx.x * AT + threadIdx.x;
+    const long long per_src = 3 * p.gstride;
+    if (t >= per_src * p.nsrc) return;
+    const long long u = t % per_src;
+    const int c = (int)(u / p.gstride);
+    const long long g = u - (long long)c * p.gstride;
+    const float *ce = c == 0 ? p.ce1 : (c == 1 ? p.ce2 : p.ce3);
+    const float v = p.grad32[t];
+    if (v != 0.f) {
+        p.grad[t] += (double)v / (double)ce[g];
+        p.grad32[t] = 0.f;
+    }
+}
+
+void launch_adj_flush(const AdjParams &p, hipStream_t st) {
+    const long long total = 3 * p.gstride * p.nsrc;
+    const dim3 grid((unsigned)((total + AT - 1) / AT)), block(AT);
+    hipLaunchKernelGGL(adj_flush, grid, block, 0, st, p);
+}
+
 void launch_adj_filter(bool rev_h, const AdjParams &p, hipStream_t st) {
     const long long per_src = (long long)2 * p.nb * ((long long)p.n3 * p.n2 + (long long)p.n3 * p.n1 +
                                                       (long long)p.n2 * p.n1);
@@ -220,20 +348,19 @@ void launch_adj_filter(bool rev_h, const AdjParams &p, hipStream_t st) {
 }
 
 template <bool REV_H>
-static void gather(int r, const AdjParams &p, hipStream_t st) {
-    const long long total = (long long)p.n2 * p.pitch * p.nsrc;
-    const dim3 grid((unsigned)((total + AT - 1) / AT)), block(AT);
+static void tiled(int r, const AdjParams &p, hipStream_t st) {
+    const dim3 grid(p.nstencil), block(kTileX * kTileY);
     switch (r) {
-    case 1: hipLaunchKernelGGL((adj_gather<1, REV_H>), grid, block, 0, st, p); break;
-    case 2: hipLaunchKernelGGL((adj_gather<2, REV_H>), grid, block, 0, st, p); break;
-    case 3: hipLaunchKernelGGL((adj_gather<3, REV_H>), grid, block, 0, st, p); break;
-    default: hipLaunchKernelGGL((adj_gather<4, REV_H>), grid, block, 0, st, p); break;
+    case 1: hipLaunchKernelGGL((adj_tile<1, REV_H>), grid, block, 0, st, p); break;
+    case 2: hipLaunchKernelGGL((adj_tile<2, REV_H>), grid, block, 0, st, p); break;
+    case 3: hipLaunchKernelGGL((adj_tile<3, REV_H>), grid, block, 0, st, p); break;
+    default: hipLaunchKernelGGL((adj_tile<4, REV_H>), grid, block, 0, st, p); break;
     }
 }
 
-void launch_adj_gather(int r, bool rev_h, const AdjParams &p, hipStream_t st) {
-    if (rev_h) gather<true>(r, p, st);
-    else gather<false>(r, p, st);
+void launch_adj_tile(int r, bool rev_h, const AdjParams &p, hipStream_t st) {
+    if (rev_h) tiled<true>(r, p, st);
+    else tiled<false>(r, p, st);
 }
 
 void launch_adj_inject(const InjectParams &p, int n, hipStream_t st) {

@@ -22,6 +22,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kMu0 = 4.0e-7 * kPi;
+constexpr int kFlush = 16;       // steps per FP32 partial sum of the gradient
 
 thread_local std::string g_last_error;
 
@@ -74,7 +75,7 @@ struct emm_model {
     DevBuf stepdev;                                 // device step counter of graph replays
     // adjoint: Et|Hb fields, Q (12 slab arrays), T (6), E snapshots, per-source
     // gradients, transposed tables, injection lists and coefficients
-    DevBuf adjf, adjq, adjt, snaps, grad, tabT, inj, injA, adjcpml;
+    DevBuf adjf, adjq, adjt, snaps, grad, grad32, tabT, inj, injA, adjcpml;
     Acq acq;
     std::map<int, std::pair<int, int>> tuned;       // autotuned (z chunk, stream hint) per source count
     hipEvent_t ev_loop[2] = {nullptr, nullptr};
@@ -215,7 +216,7 @@ void emm_destroy(emm_model *m) {
     for (float *p : m->tab) if (p) (void)hipFree(p);
     for (DevBuf *b : {&m->fields, &m->psi, &m->acc, &m->cpml, &m->srcinfo, &m->srcq, &m->wav,
                       &m->items, &m->itemw, &m->phase, &m->ckpts, &m->ickpts, &m->adjf, &m->adjq, &m->adjt,
-                      &m->snaps, &m->grad, &m->tabT, &m->inj, &m->injA, &m->adjcpml, &m->stepdev})
+                      &m->snaps, &m->grad, &m->grad32, &m->tabT, &m->inj, &m->injA, &m->adjcpml, &m->stepdev})
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : m->ev_loop) if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : m->ring) if (e) (void)hipEventDestroy(e);
@@ -1215,15 +1216,16 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
         const size_t S = state_floats(m) * A0.nsrc * sizeof(float);
         const size_t F = (size_t)3 * A0.nsrc * fs * sizeof(float);
         const size_t slab_src = (state_floats(m) - 6 * fs) / 2;     // 6 slab arrays per source
-        const size_t need[4] = {(size_t)6 * A0.nsrc * fs * sizeof(float),
+        const size_t need[5] = {(size_t)6 * A0.nsrc * fs * sizeof(float),
                                 std::max<size_t>(1, 2 * A0.nsrc * slab_src) * sizeof(float),
                                 std::max<size_t>(1, A0.nsrc * slab_src) * sizeof(float),
-                                (size_t)3 * A0.nsrc * fs * sizeof(double)};
-        const DevBuf *have[4] = {&m->adjf, &m->adjq, &m->adjt, &m->grad};
+                                (size_t)3 * A0.nsrc * fs * sizeof(double),
+                                (size_t)3 * A0.nsrc * fs * sizeof(float)};
+        const DevBuf *have[5] = {&m->adjf, &m->adjq, &m->adjt, &m->grad, &m->grad32};
         size_t fr = 0, tot = 0;
         HIP_OK(m, hipMemGetInfo(&fr, &tot));
         long long budget = (long long)fr + (long long)(m->ckpts.bytes + m->ickpts.bytes + m->snaps.bytes);
-        for (int b = 0; b < 4; ++b) budget -= (long long)(need[b] > have[b]->bytes ? need[b] - have[b]->bytes : 0);
+        for (int b = 0; b < 5; ++b) budget -= (long long)(need[b] > have[b]->bytes ? need[b] - have[b]->bytes : 0);
         budget -= (long long)(tot / 50) + (256LL << 20);
         const size_t bud = budget > 0 ? (size_t)budget : 0;
         if (!plan_checkpoints(A0.nt, m->opt.graph_steps, reuse ? A0.ckpt : m->opt.checkpoint_every,
@@ -1332,9 +1334,11 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
         (st = ensure(m, m->ickpts, (size_t)((ckpt + cin - 1) / cin) * state_floats(m) * nsrc * sizeof(float))) != EMM_OK)
         return st;
     if ((st = ensure(m, m->grad, (size_t)3 * nsrc * fstride * sizeof(double))) != EMM_OK) return st;
+    if ((st = ensure(m, m->grad32, (size_t)3 * nsrc * fstride * sizeof(float))) != EMM_OK) return st;
     HIP_OK(m, hipMemsetAsync(m->adjf.p, 0, (size_t)6 * nsrc * fstride * sizeof(float), stream));
     if (nb) HIP_OK(m, hipMemsetAsync(m->adjq.p, 0, (size_t)2 * nsrc * slab_src * sizeof(float), stream));
     HIP_OK(m, hipMemsetAsync(m->grad.p, 0, (size_t)3 * nsrc * fstride * sizeof(double), stream));
+    HIP_OK(m, hipMemsetAsync(m->grad32.p, 0, (size_t)3 * nsrc * fstride * sizeof(float), stream));
 
     // receiver injection lists (CSR over target cells, fixed order): E channels
     // target Et (scaled by dt/eps), H channels target Hb
@@ -1450,6 +1454,11 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     PE.r = r;
     PE.nb = nb;
     PE.nsrc = nsrc;
+    PE.kz = A.Pe.kz;                          // tiles and z chunks of the forward kernels
+    PE.xt = A.Pe.xt;
+    PE.yt = A.Pe.yt;
+    PE.zc = A.Pe.zc;
+    PE.nstencil = PE.xt * PE.yt * PE.zc * nsrc;
     PE.fstride = fstride;
     PE.ce1 = m->ce[0];
     PE.ce2 = m->ce[1];
@@ -1463,6 +1472,7 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     PE.szs = szs;
     PE.gstride = fstride;
     PE.grad = (double *)m->grad.p;
+    PE.grad32 = (float *)m->grad32.p;
     PH = PE;
     PE.in1 = Hb[0];
     PE.in2 = Hb[1];
@@ -1517,13 +1527,16 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
         }
         for (int n = nend - 1; n >= n0; --n) {
             if (nb) emm::launch_adj_filter(true, PE, stream);
-            emm::launch_adj_gather(r, true, PE, stream);
+            emm::launch_adj_tile(r, true, PE, stream);
             emm::launch_adj_inject(IE, n, stream);
             PH.E_next = snap + (size_t)(n - n0 + 1) * 3 * nsrc * fstride;
             PH.E_prev = snap + (size_t)(n - n0) * 3 * nsrc * fstride;
             if (nb) emm::launch_adj_filter(false, PH, stream);
-            emm::launch_adj_gather(r, false, PH, stream);
+            emm::launch_adj_tile(r, false, PH, stream);
             emm::launch_adj_inject(IH, n, stream);
+            // FP32 partial gradient sums cover the steps down to a multiple
+            // of kFlush: the same steps under every checkpoint schedule
+            if (n % kFlush == 0) emm::launch_adj_flush(PH, stream);
         }
         HIP_OK(m, hipGetLastError());
         return EMM_OK;

@@ -56,6 +56,14 @@ struct StepParams {
     const int *step_base;
 };
 
+// Hardware dispatches workgroup w to XCD w % 8; give every XCD one
+// contiguous range of logical tiles.
+__device__ __forceinline__ int xcd_tile(int w, int total) {
+    const int q = total >> 3, rem = total & 7;
+    const int x = w & 7, local = w >> 3;
+    return x * q + min(x, rem) + local;
+}
+
 void launch_e_step(int r, const StepParams &p, int n, hipStream_t s);
 void launch_advance(int *step, int k, hipStream_t s);
 void launch_h_step(int r, const StepParams &p, int n, hipStream_t s);

@@ -46,14 +46,6 @@ __device__ __forceinline__ void st1(float *p, float v) {
     else *p = v;
 }
 
-// Hardware dispatches workgroup w to XCD w % 8; give every XCD one
-// contiguous range of logical tiles.
-__device__ __forceinline__ int xcd_tile(int w, int total) {
-    const int q = total >> 3, rem = total & 7;
-    const int x = w & 7, local = w >> 3;
-    return x * q + min(x, rem) + local;
-}
-
 // Receiver sample + DTFT: one wavefront per (source, receiver, channel)
 // item.  u = sum over the (2r)^3 tensor-product stencil of w * F, reduced in
 // FP64; then acc[f] += u * exp(i w'_f t_n) for every frequency.

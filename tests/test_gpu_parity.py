@@ -144,6 +144,25 @@ def test_marine_layered_full_size_vs_stored_oracle(emm):
     assert rep["ok"], rep
 
 
+@pytest.mark.slow
+def test_large_marine_full_size_r4_batched(emm):
+    """The 400 x 400 x 200 grid (438 x 438 x 238 padded cells) at 8th order
+    with all 8 sources in one batched launch, the compensated FP32 DTFT,
+    autotuned tiles and graph replays, as the large-grid benchmark runs it.
+    The run is cut to 160 steps with a 25 Hz wavelet peak (pulse centre at
+    step 124) so the FP64 oracle finishes in about a minute; source 3 is
+    held against it."""
+    nt, fp, s = 160, 25.0, 3
+    w = configs.large_marine(nt=nt, rd=4, nsrc=8)
+    G, info = _run(emm, w, tile_kz=-1, graph_steps=64, wavelet_fpeak=fp)
+    G_o, info_o = F.forward(w.with_(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1]),
+                            threads=min(16, os.cpu_count() or 1), nt=nt, fpeak=fp)
+    assert info["dt"] == pytest.approx(info_o["dt"], rel=1e-12)
+    rep = compare(G[s:s + 1], G_o, w.channels)
+    print(f"[parity] large_marine r=4 8 sources, source {s}: {rep}", flush=True)
+    assert rep["ok"], rep
+
+
 def test_error_paths_on_device(emm):
     w = configs.small_case(seed=11, shape=(21, 20, 19), nt=50)
     with emm.Model(w) as m:
