@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc FETCH_SIZE (x 2.0) and --pmc WRITE_SIZE (x 1.0), the factors
 # from a 1 GiB copy kernel: 68 651 KiB read and 46 148 KiB written.  Valid for
 # the kernel as profiled; set to None when the kernel changes until re-measured.
-E_STEP_TRAFFIC_BYTES = (68651 * 2.0 + 46148 * 1.0) * 1024
+E_STEP_TRAFFIC_BYTES = None
 
 
 def log(*a):
@@ -170,8 +170,8 @@ def main():
                     help="sources of the batched comparison (0: skip)")
     ap.add_argument("--grad-group", type=int, default=8)
     ap.add_argument("--grad-ckpt", type=int, default=128)
-    ap.add_argument("--multi-model", action="store_true",
-                    help="also time 8 models of uneven sizes in one hipGraph vs one after another")
+    ap.add_argument("--no-multi-model", action="store_true",
+                    help="skip timing 8 models of uneven sizes in one hipGraph vs one after another")
     ap.add_argument("--large-fwd-grad", type=int, default=0, metavar="NT",
                     help="also time the 8-source 8th-order forward + gradient on the 400x400x200 "
                          "grid with NT time steps (0: skip)")
@@ -266,7 +266,7 @@ def main():
         log(f"[bench] batched comparison with {args.batched} sources")
         out["batched"] = batched_comparison(emm, w, args.batched, args.grad_group, args.grad_ckpt)
         log(f"[bench] batched: {out['batched']}")
-    if args.multi_model:
+    if not args.no_multi_model and args.workload == "marine":
         log("[bench] multi-model comparison")
         out["multi_model"] = multi_model_comparison(emm, args.graph or 64)
         log(f"[bench] multi-model: {out['multi_model']}")

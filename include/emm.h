@@ -88,6 +88,9 @@ typedef struct {
     int    checkpoint_inner; /* > 0 and < the outer interval: emm_gradient re-runs each outer
                               segment once to lay inner checkpoints this many steps apart
                               (two levels); 0: planned [0] */
+    int    nontemporal;    /* stencil kernels move the arrays they touch once with nontemporal
+                              hints: 1 = yes, 0 = no, -1 = autotuned with tile_kz = -1, else
+                              yes when the fields and dt/eps exceed 160 MiB [-1] */
 } emm_options;
 
 /* A point electric dipole (Section 5, "Survey acquisitions"): position in

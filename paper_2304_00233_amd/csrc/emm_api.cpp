@@ -151,6 +151,7 @@ int choose_kz(const emm_model *m, int xt, int yt, int nsrc) {
 // and dt/eps) exceed 160 MiB, well inside the 256 MB Infinity Cache below
 // that; the autotuner overrides this with a measurement.
 int choose_stream(const emm_model *m, long long fstride, int nsrc) {
+    if (m->opt.nontemporal >= 0) return m->opt.nontemporal;
     if (m->opt.tile_kz < 0) {
         auto it = m->tuned.find(nsrc);
         if (it != m->tuned.end()) return it->second.second;
@@ -184,6 +185,7 @@ emm_status emm_default_options(emm_options *o) {
     o->checkpoint_every = 0;
     o->graph_steps = 0;
     o->checkpoint_inner = 0;
+    o->nontemporal = -1;
     return EMM_OK;
 }
 
@@ -241,7 +243,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (!(opt.f0 > 0.0) || !std::isfinite(opt.f0)) return fail(nullptr, EMM_ERR_ARG, "f0 must be > 0");
     if (!(opt.cfl > 0.0) || !std::isfinite(opt.cfl)) return fail(nullptr, EMM_ERR_ARG, "cfl must be > 0");
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
-        opt.checkpoint_inner < 0 ||
+        opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -1105,6 +1107,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     const int steps = 8;
     for (int st : {0, 1})
         for (int kz : cand) {
+            if (m->opt.nontemporal >= 0 && st != m->opt.nontemporal) continue;
             if (kz > nzv) continue;
             emm::StepParams Pe = A.Pe, Ph = A.Ph;
             Pe.kz = Ph.kz = kz;

@@ -138,7 +138,13 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     const int byt = t % p.yt;
     const int bzt = t / p.yt;
 
-    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    // The row index is wave-uniform (one row per wavefront); declaring it so
+    // moves the y coefficients and y-slab values to scalar registers.  That
+    // frees vector registers but adds scalar spills; measured, it pays in
+    // the E step and in the H step at 8th order only.
+    constexpr bool kScalarRow = !HS || R >= 4;
+    const int tid = threadIdx.x, tx = tid & 63;
+    const int ty = kScalarRow ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
     const int i0 = bxt * kTileX, j0 = R + byt * TY;
     const int i = i0 + tx, j = j0 + ty;
     const int k0 = R + bzt * p.kz;

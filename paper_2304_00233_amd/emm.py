@@ -45,7 +45,7 @@ class emm_options(C.Structure):
                 ("cpml_alpha_max", C.c_double), ("wavelet_fpeak", C.c_double),
                 ("allow_unstable", C.c_int), ("profile", C.c_int), ("tile_kz", C.c_int),
                 ("checkpoint_every", C.c_int), ("graph_steps", C.c_int),
-                ("checkpoint_inner", C.c_int)]
+                ("checkpoint_inner", C.c_int), ("nontemporal", C.c_int)]
 
 
 class emm_source(C.Structure):

@@ -59,6 +59,7 @@ def test_default_options(emm):
     assert (o.rd, o.nb, o.ne, o.f0, o.cfl, o.nt, o.dft_mode) == (2, 10, -1, 1.0, 0.99, 0, 0)
     assert o.cpml_R == 1e-5 and o.cpml_npow == 2.0 and o.profile == 0
     assert (o.checkpoint_every, o.checkpoint_inner, o.graph_steps, o.tile_kz) == (0, 0, 0, 0)
+    assert o.nontemporal == -1
 
 
 def test_status_strings(emm):

@@ -106,6 +106,14 @@ def test_batched_equals_single_sources(emm):
         assert np.array_equal(Gb[s:s + 1], Gs)
 
 
+def test_nontemporal_hint_is_bitwise_neutral(emm):
+    w = configs.small_case(seed=12, shape=(30, 26, 22), nt=120)
+    G0, i0 = _run(emm, w, nontemporal=0)
+    G1, i1 = _run(emm, w, nontemporal=1)
+    assert (i0["nontemporal"], i1["nontemporal"]) == (0, 1)
+    assert np.array_equal(G0, G1)
+
+
 def test_multi_model_batch_equals_single_forwards(emm):
     """Models of uneven sizes, step counts and source counts in one hipGraph
     (32 steps per block: every job ends with a ragged remainder, and the
