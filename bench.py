@@ -26,9 +26,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # HBM traffic of one E-step launch on the marine workload, measured with
 # rocprofv3 --pmc FETCH_SIZE (x 2.0) and --pmc WRITE_SIZE (x 1.0), the factors
-# from a 1 GiB copy kernel: 68 651 KiB read and 46 148 KiB written.  Valid for
+# from a 1 GiB copy kernel: 69 207.9 KiB read and 46 142.1 KiB written.  Valid for
 # the kernel as profiled; set to None when the kernel changes until re-measured.
-E_STEP_TRAFFIC_BYTES = None
+E_STEP_TRAFFIC_BYTES = (69207.9 * 2.0 + 46142.1 * 1.0) * 1024
 
 
 def log(*a):
@@ -177,6 +177,9 @@ def main():
                          "grid with NT time steps (0: skip)")
     ap.add_argument("--large-group", type=int, default=2,
                     help="sources per emm_gradient call of --large-fwd-grad")
+    ap.add_argument("--gradient-sample", type=int, default=0, metavar="NT",
+                    help="only run one forward + gradient of the marine workload cut to NT steps "
+                         "(for kernel traces of the adjoint) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -188,6 +191,19 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         log(f"[bench] copied {a.numel() * 4} bytes")
+        return
+    if args.gradient_sample:
+        from paper_2304_00233_amd import emm
+        from workloads import configs
+        w = configs.marine_layered(nt=args.gradient_sample)
+        with emm.Model(w, tile_kz=-1, graph_steps=64) as m:
+            G = m.forward()
+            t = time.perf_counter()
+            m.gradient(g_obs=G * 1.01)
+            dt = time.perf_counter() - t
+            i = m.info()
+        log(f"[bench] gradient sample: {w.name}, {args.gradient_sample} steps, forward + gradient "
+            f"{dt * 1e3:.1f} ms, checkpoints every {i['ckpt_outer']} (inner {i['ckpt_inner']})")
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by "

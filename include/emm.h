@@ -74,9 +74,10 @@ typedef struct {
     double cpml_alpha_max; /* frequency-shift maximum; 0 = pi * f_peak [0] */
     double wavelet_fpeak;  /* source wavelet peak frequency; 0 = 2 sqrt(f_max f0) [0] */
     int    allow_unstable; /* test hook: accept dt_override above the CFL limit [0] */
-    int    profile;        /* 1 = time stencil launches with HIP events: one E/H pair in 16
-                              direct steps; with graph_steps, every 8th block of steps runs as
-                              direct launches and one pair in 4 of them is timed (emm_query) [0] */
+    int    profile;        /* 1 = time stencil launches with HIP events that the dispatch
+                              stamps at kernel start and end (hipExtLaunchKernel): one E/H pair
+                              in 16 direct steps; with graph_steps, every 8th block of steps runs
+                              as direct launches and one pair in 4 of them is timed (emm_query) [0] */
     int    tile_kz;        /* z planes per thread block; 0 = chosen from the grid, -1 = autotuned
                               together with the nontemporal hint on the first forward (timing
                               candidates on this model) [0] */

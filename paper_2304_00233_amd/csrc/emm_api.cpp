@@ -815,8 +815,9 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         const int nck = (nt + ckpt - 1) / ckpt;
         if ((st = ensure(m, m->ckpts, (size_t)nck * state_floats(m) * nsrc * sizeof(float))) != EMM_OK) return st;
     }
-    // Profiling: HIP events bracket one E step and one H step out of every
-    // `sample` direct launches.  With graph replays (event nodes in graphs
+    // Profiling: HIP events stamped by the dispatch of one E step and one H
+    // step out of every `sample` direct launches give those kernels' start
+    // and end.  With graph replays (event nodes in graphs
     // carry no timestamps here), every 8th block of K steps is launched
     // directly instead -- the same kernels with the absolute step index --
     // and sampled, so the timing is taken inside the timed loop.
@@ -853,15 +854,14 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
                 if (s2 != EMM_OK) return s2;
             }
             ++nslots_used;
-            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 0], stream));
         }
-        emm::launch_e_step(r, A.Pe, n, stream);
-        if (timed) {
-            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 1], stream));
-            HIP_OK(m, hipEventRecord(m->ring[4 * slot + 2], stream));
-        }
-        emm::launch_h_step(r, A.Ph, n, stream);
-        if (timed) HIP_OK(m, hipEventRecord(m->ring[4 * slot + 3], stream));
+        // timed launches carry their events in the dispatch itself (kernel
+        // start and end, as a kernel trace reports them)
+        emm::launch_e_step(r, A.Pe, n, stream, timed ? m->ring[4 * slot + 0] : nullptr,
+                           timed ? m->ring[4 * slot + 1] : nullptr);
+        emm::launch_h_step(r, A.Ph, n, stream, timed ? m->ring[4 * slot + 2] : nullptr,
+                           timed ? m->ring[4 * slot + 3] : nullptr);
+        HIP_OK(m, hipGetLastError());
         return EMM_OK;
     };
     HIP_OK(m, hipEventRecord(m->ev_loop[0], stream));

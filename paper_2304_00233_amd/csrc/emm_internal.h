@@ -64,9 +64,13 @@ __device__ __forceinline__ int xcd_tile(int w, int total) {
     return x * q + min(x, rem) + local;
 }
 
-void launch_e_step(int r, const StepParams &p, int n, hipStream_t s);
+// t0/t1 (optional): events stamped with the kernel's own start and end
+// (hipExtLaunchKernel), i.e. the duration a kernel trace reports
+void launch_e_step(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);
 void launch_advance(int *step, int k, hipStream_t s);
-void launch_h_step(int r, const StepParams &p, int n, hipStream_t s);
+void launch_h_step(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);
 int block_threads();
 
 }  // namespace emm

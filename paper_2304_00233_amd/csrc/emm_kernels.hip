@@ -28,6 +28,8 @@
 // ranges so that neighbouring tiles share an L2.
 #include "emm_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace emm {
 
 constexpr int TY = kTileY;
@@ -365,20 +367,26 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     }
 }
 
-template <bool HS, bool ST>
-static void launch(int r, const StepParams &p, int n, hipStream_t s) {
+template <int R, bool HS, bool ST>
+static void launch_r(const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const dim3 grid(p.nrecblk + p.nstencil), block(NT);
+    if (t0 || t1) hipExtLaunchKernelGGL((step_kernel<R, HS, ST>), grid, block, 0, s, t0, t1, 0, p, n);
+    else hipLaunchKernelGGL((step_kernel<R, HS, ST>), grid, block, 0, s, p, n);
+}
+
+template <bool HS, bool ST>
+static void launch(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     switch (r) {
-    case 1: hipLaunchKernelGGL((step_kernel<1, HS, ST>), grid, block, 0, s, p, n); break;
-    case 2: hipLaunchKernelGGL((step_kernel<2, HS, ST>), grid, block, 0, s, p, n); break;
-    case 3: hipLaunchKernelGGL((step_kernel<3, HS, ST>), grid, block, 0, s, p, n); break;
-    default: hipLaunchKernelGGL((step_kernel<4, HS, ST>), grid, block, 0, s, p, n); break;
+    case 1: launch_r<1, HS, ST>(p, n, s, t0, t1); break;
+    case 2: launch_r<2, HS, ST>(p, n, s, t0, t1); break;
+    case 3: launch_r<3, HS, ST>(p, n, s, t0, t1); break;
+    default: launch_r<4, HS, ST>(p, n, s, t0, t1); break;
     }
 }
 
-void launch_e_step(int r, const StepParams &p, int n, hipStream_t s) {
-    if (p.stream) launch<false, true>(r, p, n, s);
-    else launch<false, false>(r, p, n, s);
+void launch_e_step(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if (p.stream) launch<false, true>(r, p, n, s, t0, t1);
+    else launch<false, false>(r, p, n, s, t0, t1);
 }
 
 // graph replays: advance the device step counter by k after each replay
@@ -389,9 +397,9 @@ __global__ void advance_kernel(int *step, int k) {
 void launch_advance(int *step, int k, hipStream_t s) {
     hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, step, k);
 }
-void launch_h_step(int r, const StepParams &p, int n, hipStream_t s) {
-    if (p.stream) launch<true, true>(r, p, n, s);
-    else launch<true, false>(r, p, n, s);
+void launch_h_step(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    if (p.stream) launch<true, true>(r, p, n, s, t0, t1);
+    else launch<true, false>(r, p, n, s, t0, t1);
 }
 
 }  // namespace emm
