@@ -158,9 +158,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2000)
-    ap.add_argument("--workload", default="marine", choices=["marine", "large", "cube"],
+    ap.add_argument("--workload", default="marine", choices=["marine", "large", "cube", "shallow"],
                     help="marine: the headline 128x128x96 workload; large: the 400x400x200 "
-                         "marine grid (one source); cube: uniform n^3 (--cube-n)")
+                         "marine grid (one source); cube: uniform n^3 (--cube-n); shallow: "
+                         "128x128x80 shallow water with the air boundary")
     ap.add_argument("--cube-n", type=int, default=400)
     ap.add_argument("--rd", type=int, default=0, help="override the stencil half length")
     ap.add_argument("--nt", type=int, default=0, help="override the time-step count")
@@ -220,6 +221,11 @@ def main():
         if os.path.exists(gold):
             nt = json.load(open(gold))["nt"]
         w = w.with_(nt=nt)
+    elif args.workload == "shallow":
+        w = configs.shallow_marine()
+        gold = os.path.join(ROOT, "tests", "golden", "shallow_marine_air_oracle.json")
+        if os.path.exists(gold):
+            w = w.with_(nt=json.load(open(gold))["nt"])
     elif args.workload == "large":
         w = configs.large_marine(nsrc=1).with_(dft_mode=0)
     else:

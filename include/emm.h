@@ -92,6 +92,12 @@ typedef struct {
     int    nontemporal;    /* stencil kernels move the arrays they touch once with nontemporal
                               hints: 1 = yes, 0 = no, -1 = autotuned with tile_kz = -1, else
                               yes when the fields and dt/eps exceed 160 MiB [-1] */
+    int    airwave;        /* 1: the first z node is the sea (or land) surface with air above it
+                              (Section 3.3): no cell above it is updated and the ghost planes the
+                              stencils reach are filled after each half step by 2-D FFTs (H as a
+                              potential field, E harmonic); needs uniform x and y spacing
+                              (EMM_ERR_GRID otherwise); time steps run as direct launches;
+                              emm_gradient and emm_forward_batch refuse it (EMM_ERR_ARG) [0] */
 } emm_options;
 
 /* A point electric dipole (Section 5, "Survey acquisitions"): position in

@@ -24,6 +24,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from . import airwave as AW
 from . import tables as T
 
 
@@ -56,8 +57,50 @@ def _lift(op, axis, n_pad):
     return sp.kron(mats[0], sp.kron(mats[1], mats[2], format="csr"), format="csr")
 
 
-def solve(st, freq: float, src, comp: int, rec, chans, moment: float = 1.0):
-    """Receiver values of E^ / H^ per unit source spectrum: [nrec][nchan]."""
+def _ghost_maps(st):
+    """The air boundary's ghost fills as sparse maps on the [3][z][y][x]
+    vectors: P_E = I + (E1, E2 ghost planes from the surface plane), P_H =
+    I + (H1, H2 ghost half planes from H3 at the surface).  Built column by
+    column by applying the fills of `airwave` to unit surface planes; the
+    ghost fill is linear and uses only same-time-level values, so the
+    z-transform carries it over unchanged."""
+    n1, n2, n3 = st.n_pad
+    N, M = n1 * n2 * n3, n1 * n2
+    ops = AW.make_ops(st.axes, st.nbe, st.r)
+    ks = st.nbe
+    rowsE, colsE, valsE, rowsH, colsH, valsH = [], [], [], [], [], []
+    for q in range(M):
+        unit = np.zeros((n3, n2, n1))
+        unit.reshape(n3, M)[ks, q] = 1.0
+        a, b = unit.copy(), unit.copy()
+        AW.fill_E(a, b, ops)
+        h1, h2 = np.zeros((n3, n2, n1)), np.zeros((n3, n2, n1))
+        AW.fill_H(h1, h2, unit, ops)
+        for m in range(1, st.r + 1):
+            for c, F in ((0, a), (1, b)):
+                if m < st.r:
+                    v = F.reshape(n3, M)[ks - m]
+                    nz = np.nonzero(v)[0]
+                    rowsE += list(c * N + (ks - m) * M + nz)
+                    colsE += [c * N + ks * M + q] * len(nz)
+                    valsE += list(v[nz])
+            for c, F in ((0, h1), (1, h2)):
+                v = F.reshape(n3, M)[ks - m]
+                nz = np.nonzero(v)[0]
+                rowsH += list(c * N + (ks - m) * M + nz)
+                colsH += [2 * N + ks * M + q] * len(nz)
+                valsH += list(v[nz])
+    I = sp.identity(3 * N, format="csr")
+    PE = I + sp.csr_matrix((valsE, (rowsE, colsE)), shape=(3 * N, 3 * N))
+    PH = I + sp.csr_matrix((valsH, (rowsH, colsH)), shape=(3 * N, 3 * N))
+    return PE, PH
+
+
+def solve(st, freq: float, src, comp: int, rec, chans, moment: float = 1.0,
+          airwave: bool = False):
+    """Receiver values of E^ / H^ per unit source spectrum: [nrec][nchan].
+    airwave: the first interior z node is the sea surface with air above
+    (updates start there; ghost planes above it, `airwave`)."""
     n1, n2, n3 = st.n_pad
     N = n1 * n2 * n3
     r = st.r
@@ -70,8 +113,9 @@ def solve(st, freq: float, src, comp: int, rec, chans, moment: float = 1.0):
         Dm.append(_lift(m, a, st.n_pad))
         Dp.append(_lift(p, a, st.n_pad))
     k, j, i = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    kmin = st.nbe if airwave else r
     upd = ((i >= r) & (i <= n1 - 1 - r) & (j >= r) & (j <= n2 - 1 - r) &
-           (k >= r) & (k <= n3 - 1 - r)).ravel().astype(np.float64)
+           (k >= kmin) & (k <= n3 - 1 - r)).ravel().astype(np.float64)
     U = sp.diags(upd)
     Z = sp.csr_matrix((N, N))
     # curl H~ -> E positions; curl E~ -> H positions (rows masked to the update set)
@@ -80,6 +124,10 @@ def solve(st, freq: float, src, comp: int, rec, chans, moment: float = 1.0):
     U3 = sp.block_diag([U, U, U], format="csr")
     curlH = U3 @ curlH
     curlE = U3 @ curlE
+    if airwave:
+        PE, PH = _ghost_maps(st)
+        curlH = (curlH @ PH).tocsr()
+        curlE = (curlE @ PE).tocsr()
     ce = np.concatenate([c.ravel() for c in st.ce])
     ch = st.dt / T.MU0
     Ce = sp.diags(ce)

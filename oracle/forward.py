@@ -16,6 +16,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from . import airwave as AW
 from . import tables as T
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +44,8 @@ class _Params(C.Structure):
         ("phE_re", _dp), ("phE_im", _dp), ("phH_re", _dp), ("phH_im", _dp),
         ("acc_re", _dp), ("acc_im", _dp),
         ("nthreads", C.c_int),
+        ("kmin", C.c_int),
+        ("ghost", C.c_void_p),
     ]
 
 
@@ -64,6 +67,24 @@ def _load():
             f.argtypes = [C.POINTER(_Params)] + [_dp] * 6
             f.restype = None
     return _lib
+
+
+_GHOST_FN = C.CFUNCTYPE(None, C.c_int, C.POINTER(_dp))
+
+
+def _ghost_callback(st: "Setup"):
+    """Ghost-plane filler for the air above the surface node (Section 3.3),
+    called by the stepper after each E and each H update."""
+    ops = AW.make_ops(st.axes, st.nbe, st.r)
+    n1, n2, n3 = st.n_pad
+
+    def cb(which, fields):
+        F = [np.ctypeslib.as_array(fields[c], shape=(n3, n2, n1)) for c in range(6)]
+        if which == 0:
+            AW.fill_E(F[0], F[1], ops)
+        else:
+            AW.fill_H(F[3], F[4], F[5], ops)
+    return _GHOST_FN(cb)
 
 
 def _ptr(a, ctype=C.c_double):
@@ -166,17 +187,26 @@ def _build_params(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
     P.phE_re, P.phE_im, P.phH_re, P.phH_im = (_ptr(a) for a in (phE_re, phE_im, phH_re, phH_im))
     P.acc_re, P.acc_im = _ptr(acc_re), _ptr(acc_im)
     P.nthreads = int(threads or os.cpu_count() or 1)
+    P.kmin = r
+    P.ghost = None
     keep = (tabs, cp, q, s, ch_arr, rb, rw, phE_re, phE_im, phH_re, phH_im, acc_re, acc_im)
     return P, keep, s
 
 
 def run_source(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
-               threads: int | None = None, moment: float = 1.0):
+               threads: int | None = None, moment: float = 1.0, airwave: bool = False):
     """Time-domain run for one source; returns the receiver DTFT
-    acc[nrec][nchan][nfreq] and the source spectrum S_f."""
+    acc[nrec][nchan][nfreq] and the source spectrum S_f.  airwave: the
+    first interior z node is the sea surface with air above it."""
     lib = _load()
     P, keep, s = _build_params(st, nt, src, comp, rec, chans, freqs, threads, moment)
+    cb = None
+    if airwave:
+        cb = _ghost_callback(st)
+        P.kmin = st.nbe
+        P.ghost = C.cast(cb, C.c_void_p)
     rc = lib.oracle_run(C.byref(P))
+    del cb
     if rc < 0:
         raise MemoryError("oracle allocation failed")
     acc = keep[-2] + 1j * keep[-1]
@@ -226,6 +256,8 @@ def misfit_gradient(w, G_obs, threads: int | None = None, nt: int | None = None,
     returns (chi, grad[3][n3][n2][n1], G).  dt, the step count and the CPML
     tables are held fixed (pass `frozen`, the set-up of the reference model,
     when evaluating perturbed models)."""
+    if w.airwave:
+        raise NotImplementedError("the adjoint of the air boundary is not built")
     freqs = np.asarray(w.freqs, dtype=np.float64)
     fp = T.peak_frequency(freqs, w.f0, fpeak)
     st = make_setup(w, fp, dt_override, frozen)
@@ -278,7 +310,7 @@ def forward(w, threads: int | None = None, nt: int | None = None,
     nonfinite = False
     for s_i, src in enumerate(w.sources):
         acc, S, rc = run_source(st, nt, src, int(w.src_comp[s_i]), w.receivers,
-                                chans, freqs, threads)
+                                chans, freqs, threads, airwave=w.airwave)
         nonfinite |= rc == 1
         out[s_i] = green(acc, S, freqs, st.omega0, chans)
     info = dict(dt=st.dt, nt=nt, n_pad=st.n_pad, fp=fp, nonfinite=nonfinite)

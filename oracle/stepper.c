@@ -53,6 +53,13 @@ typedef struct {
     const double *phH_re, *phH_im;   /* [nt][nfreq] exp(i w' (n+1/2) dt) */
     double *acc_re, *acc_im;   /* [nrec][nchan][nfreq] out */
     int nthreads;
+    /* first updated z plane: r, or the sea-surface node when the air above
+     * it is handled by ghost planes (Section 3.3) */
+    int kmin;
+    /* called after every E update (which = 0) and H update (which = 1) with
+     * the six fields {E1, E2, E3, H1, H2, H3}; fills the ghost planes above
+     * kmin (NULL: none) */
+    void (*ghost)(int which, double **fields);
 } oracle_params;
 
 #define IDX(k, j, i) (((size_t)(k) * n2 + (size_t)(j)) * n1 + (size_t)(i))
@@ -67,7 +74,7 @@ static void curl_h(const oracle_params *p, const double *H1, const double *H2,
 {
     const int n1 = p->n1, n2 = p->n2, n3 = p->n3, r = p->r, nb = p->nb;
 #pragma omp parallel for num_threads(p->nthreads) schedule(static)
-    for (int k = r; k <= n3 - 1 - r; k++) {
+    for (int k = p->kmin; k <= n3 - 1 - r; k++) {
         for (int j = r; j <= n2 - 1 - r; j++) {
             for (int i = r; i <= n1 - 1 - r; i++) {
                 double D2H3 = 0, D3H2 = 0, D3H1 = 0, D1H3 = 0, D1H2 = 0, D2H1 = 0;
@@ -114,7 +121,7 @@ static void curl_e(const oracle_params *p, const double *E1, const double *E2,
 {
     const int n1 = p->n1, n2 = p->n2, n3 = p->n3, r = p->r, nb = p->nb;
 #pragma omp parallel for num_threads(p->nthreads) schedule(static)
-    for (int k = r; k <= n3 - 1 - r; k++) {
+    for (int k = p->kmin; k <= n3 - 1 - r; k++) {
         for (int j = r; j <= n2 - 1 - r; j++) {
             for (int i = r; i <= n1 - 1 - r; i++) {
                 double D2E3 = 0, D3E2 = 0, D3E1 = 0, D1E3 = 0, D1E2 = 0, D2E1 = 0;
@@ -158,7 +165,7 @@ static void update(const oracle_params *p, double *F, const double *coef,
 {
     const int n1 = p->n1, n2 = p->n2, n3 = p->n3, r = p->r;
 #pragma omp parallel for num_threads(p->nthreads) schedule(static)
-    for (int k = r; k <= n3 - 1 - r; k++)
+    for (int k = p->kmin; k <= n3 - 1 - r; k++)
         for (int j = r; j <= n2 - 1 - r; j++)
             for (int i = r; i <= n1 - 1 - r; i++) {
                 size_t id = IDX(k, j, i);
@@ -195,6 +202,7 @@ int oracle_run(const oracle_params *p)
     double *c1 = buf + 6 * N, *c2 = buf + 7 * N, *c3 = buf + 8 * N;
     double *m = buf + 9 * N;  /* m[0..5]: curl-H memories, m[6..11]: curl-E */
     double *E[3] = {E1, E2, E3}, *H[3] = {H1, H2, H3}, *cH[3] = {c1, c2, c3};
+    double *F6[6] = {E1, E2, E3, H1, H2, H3};
     memset(p->acc_re, 0, sizeof(double) * p->nrec * p->nchan * nf);
     memset(p->acc_im, 0, sizeof(double) * p->nrec * p->nchan * nf);
 
@@ -214,6 +222,7 @@ int oracle_run(const oracle_params *p)
         update(p, E1, p->ce1, 0.0, c1, 1.0);
         update(p, E2, p->ce2, 0.0, c2, 1.0);
         update(p, E3, p->ce3, 0.0, c3, 1.0);
+        if (p->ghost) p->ghost(0, F6);
         /* record E^{n+1} (stamp (n+1) dt) and H^{n+1/2} (stamp (n+1/2) dt) */
         for (int ir = 0; ir < p->nrec; ir++)
             for (int ic = 0; ic < p->nchan; ic++) {
@@ -233,6 +242,7 @@ int oracle_run(const oracle_params *p)
         update(p, H1, NULL, p->ch, c1, -1.0);
         update(p, H2, NULL, p->ch, c2, -1.0);
         update(p, H3, NULL, p->ch, c3, -1.0);
+        if (p->ghost) p->ghost(1, F6);
     }
     free(buf);
     for (size_t s = 0; s < (size_t)p->nrec * p->nchan * nf; s++)
@@ -328,6 +338,7 @@ int oracle_gradient(const oracle_params *p, int ckpt, const double *A_re,
     const size_t N = (size_t)n1 * n2 * n3;
     const int nt = p->nt, nf = p->nfreq;
     const int nseg = (nt + ckpt - 1) / ckpt;
+    if (p->kmin != r || p->ghost) return -2;      /* the adjoint of the air boundary is not built */
     /* working state: 18 N (fields + memories) + 3 N curl scratch */
     double *buf = calloc(21 * N, sizeof(double));
     double *cks = calloc((size_t)nseg * 18 * N, sizeof(double));

@@ -11,7 +11,8 @@ import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
-SOURCES = ["csrc/emm_api.cpp", "csrc/emm_setup.cpp", "csrc/emm_kernels.hip", "csrc/emm_adjoint.hip"]
+SOURCES = ["csrc/emm_api.cpp", "csrc/emm_setup.cpp", "csrc/emm_kernels.hip", "csrc/emm_adjoint.hip",
+           "csrc/emm_air.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("EMM_OFFLOAD_ARCH", "gfx950")
 
@@ -43,7 +44,8 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     if errs:
         raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
     tmp = out + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
+           "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,0 +1,47 @@
+// Air above the sea surface (Section 3.3): ghost planes above the surface
+// node filled by 2-D FFTs after each half step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <string>
+#include <vector>
+
+namespace emm {
+
+struct AirSpec {
+    int n1, n2, n3, pitch;     // padded grid; fields [n3][n2][pitch]
+    int ks, r, nsrc;           // surface node, half stencil, sources
+    long long plane, fstride;  // n2 * pitch, one source's field array
+    double dx, dy;             // uniform horizontal spacings
+    std::vector<double> hE;    // heights of the E ghost nodes ks - m, m = 1 .. r - 1
+    std::vector<double> hH;    // heights of the H ghost half nodes ks - m, m = 1 .. r
+};
+
+class AirBoundary {
+  public:
+    AirBoundary() = default;
+    AirBoundary(const AirBoundary &) = delete;
+    AirBoundary &operator=(const AirBoundary &) = delete;
+    ~AirBoundary();
+    // plans, spectral tables and work buffers; false with `err` set on failure
+    bool init(const AirSpec &spec, std::string &err);
+    const AirSpec &spec() const { return s_; }
+    // E1 (component 0, source 0; E2 follows after nsrc field arrays):
+    // E1, E2 ghost nodes from the surface plane
+    bool fill_E(float *E1, hipStream_t st, std::string &err);
+    // H1 (H2 follows), H3: H1, H2 ghost half nodes from H3 at the surface
+    bool fill_H(float *H1, const float *H3, hipStream_t st, std::string &err);
+
+  private:
+    AirSpec s_{};
+    int nbin_ = 0;                       // n2 * (n1/2 + 1)
+    hipfftHandle fwdE_ = 0, fwdH_ = 0, invE_ = 0, invH_ = 0;
+    bool have_fwdE_ = false, have_fwdH_ = false, have_invE_ = false, have_invH_ = false;
+    float2 *spec_ = nullptr, *work_ = nullptr;
+    float *decE_ = nullptr;              // [r-1][nbin] exp(-|k| h) / (n1 n2)
+    float2 *rx_ = nullptr, *ry_ = nullptr;   // [r][nbin]
+};
+
+}  // namespace emm

@@ -1,6 +1,7 @@
 // C ABI of libemm: validation, set-up, device buffers and the time loop.
 // Declarations and argument conventions: include/emm.h.
 #include "emm.h"
+#include "emm_air.h"
 
 #include <hip/hip_runtime.h>
 
@@ -10,6 +11,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -78,6 +80,7 @@ struct emm_model {
     DevBuf adjf, adjq, adjt, snaps, grad, grad32, tabT, inj, injA, adjcpml;
     Acq acq;
     std::map<int, std::pair<int, int>> tuned;       // autotuned (z chunk, stream hint) per source count
+    std::unique_ptr<emm::AirBoundary> air;          // ghost planes above the surface (airwave)
     hipEvent_t ev_loop[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ring;       // profiling: start/end pairs
     emm_info info{};
@@ -134,8 +137,13 @@ void step_bytes(const emm_model *m, double &eb, double &hb) {
     hb = 36.0 * N + 16.0 * ncpml;
 }
 
+// first updated z plane: r, or the surface node when air sits above it
+int kmin_of(const emm_model *m) { return m->opt.airwave ? m->nbe : m->r; }
+// z planes of the update set
+int z_planes(const emm_model *m) { return m->np[2] - m->r - kmin_of(m); }
+
 int choose_kz(const emm_model *m, int xt, int yt, int nsrc) {
-    const int nzv = m->np[2] - 2 * m->r;
+    const int nzv = z_planes(m);
     if (m->opt.tile_kz > 0) return std::min(m->opt.tile_kz, nzv);
     if (m->opt.tile_kz < 0) {
         auto it = m->tuned.find(nsrc);
@@ -244,6 +252,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (!(opt.cfl > 0.0) || !std::isfinite(opt.cfl)) return fail(nullptr, EMM_ERR_ARG, "cfl must be > 0");
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
         opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
+        opt.airwave < 0 || opt.airwave > 1 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -256,6 +265,18 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
             return fail(nullptr, EMM_ERR_GRID, "every axis needs at least 2*rd+1 nodes");
         if (!finite_increasing(xs[a], nd[a]))
             return fail(nullptr, EMM_ERR_GRID, "coordinates must be finite and strictly increasing");
+    }
+    if (opt.airwave) {
+        // the FFTs of the air boundary need uniform x and y spacing, and the
+        // ghost planes must fit above the surface node
+        for (int a = 0; a < 2; ++a) {
+            const double d0 = xs[a][1] - xs[a][0];
+            for (int i = 1; i < nd[a]; ++i)
+                if (std::fabs((xs[a][i] - xs[a][i - 1]) - d0) > 1e-9 * std::fabs(d0))
+                    return fail(nullptr, EMM_ERR_GRID, "the air boundary needs uniform x and y spacing");
+        }
+        if (opt.nb + opt.ne < opt.rd)
+            return fail(nullptr, EMM_ERR_GRID, "the air boundary needs nb + ne >= rd planes above the surface");
     }
     const long long ncell = (long long)nd[0] * nd[1] * nd[2];
     for (int a = 0; a < 3; ++a)
@@ -598,7 +619,8 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.xt = m->pitch / emm::kTileX;
     P.yt = (m->np[1] - 2 * r + emm::kTileY - 1) / emm::kTileY;
     P.kz = choose_kz(m, P.xt, P.yt, nsrc);
-    P.zc = (m->np[2] - 2 * r + P.kz - 1) / P.kz;
+    P.zc = (z_planes(m) + P.kz - 1) / P.kz;
+    P.kmin = kmin_of(m);
     P.nsrc = nsrc;
     P.nstencil = P.xt * P.yt * P.zc * nsrc;
     P.stream = choose_stream(m, fstride, nsrc);
@@ -686,6 +708,29 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     A.src.assign(src, src + nsrc);
     A.rec.assign(rec, rec + nrec);
     A.freqs.assign(freq_hz, freq_hz + nfreq);
+    if (m->opt.airwave && (!m->air || m->air->spec().nsrc != nsrc)) {
+        // ghost-plane FFT plans and spectral tables of the air boundary
+        emm::AirSpec as;
+        as.n1 = m->np[0];
+        as.n2 = m->np[1];
+        as.n3 = m->np[2];
+        as.pitch = m->pitch;
+        as.ks = m->nbe;
+        as.r = r;
+        as.nsrc = nsrc;
+        as.plane = plane;
+        as.fstride = fstride;
+        as.dx = m->axes[0][1] - m->axes[0][0];
+        as.dy = m->axes[1][1] - m->axes[1][0];
+        const std::vector<double> &z = m->axes[2];
+        for (int q = 1; q < r; ++q) as.hE.push_back(z[as.ks] - z[as.ks - q]);
+        for (int q = 1; q <= r; ++q) as.hH.push_back(z[as.ks] - 0.5 * (z[as.ks - q] + z[as.ks - q + 1]));
+        m->air.reset();
+        auto air = std::make_unique<emm::AirBoundary>();
+        std::string err;
+        if (!air->init(as, err)) return fail(m, EMM_ERR_DEVICE, err);
+        m->air = std::move(air);
+    }
     A.valid = true;
     return EMM_OK;
 }
@@ -857,10 +902,13 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         }
         // timed launches carry their events in the dispatch itself (kernel
         // start and end, as a kernel trace reports them)
+        std::string aerr;
         emm::launch_e_step(r, A.Pe, n, stream, timed ? m->ring[4 * slot + 0] : nullptr,
                            timed ? m->ring[4 * slot + 1] : nullptr);
+        if (m->air && !m->air->fill_E(A.Pe.E1, stream, aerr)) return fail(m, EMM_ERR_DEVICE, aerr);
         emm::launch_h_step(r, A.Ph, n, stream, timed ? m->ring[4 * slot + 2] : nullptr,
                            timed ? m->ring[4 * slot + 3] : nullptr);
+        if (m->air && !m->air->fill_H(A.Ph.H1, A.Ph.H3, stream, aerr)) return fail(m, EMM_ERR_DEVICE, aerr);
         HIP_OK(m, hipGetLastError());
         return EMM_OK;
     };
@@ -869,7 +917,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     // K steps per captured hipGraph, replayed with a device step counter;
     // checkpoints must fall on replay edges
     const int K = m->opt.graph_steps;
-    if (K > 0 && nt >= K && (ckpt == 0 || ckpt % K == 0)) {
+    if (K > 0 && nt >= K && (ckpt == 0 || ckpt % K == 0) && !m->opt.airwave) {
         if ((st = ensure(m, m->stepdev, 256)) != EMM_OK) return st;
         int *stepd = (int *)m->stepdev.p;
         HIP_OK(m, hipMemsetAsync(stepd, 0, sizeof(int), stream));
@@ -1097,7 +1145,7 @@ emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t
 emm_status autotune(emm_model *m, hipStream_t stream) {
     Acq &A = m->acq;
     if (m->opt.tile_kz >= 0 || m->tuned.count(A.nsrc)) return EMM_OK;
-    const int nzv = m->np[2] - 2 * m->r;
+    const int nzv = z_planes(m);
     std::vector<int> cand = {4, 6, 8, 12, 16, 24, 32, 48, 64, A.Pe.kz};
     hipEvent_t e0, e1;
     HIP_OK(m, hipEventCreate(&e0));
@@ -1176,6 +1224,8 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
             return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": a model may appear in one job only");
         if (m->device != jobs[0].model->device)
             return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": all models must be on one device");
+        if (m->opt.airwave)
+            return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": the air boundary runs through emm_forward only");
         m->err.clear();
         ms.push_back(m);
     }
@@ -1201,6 +1251,7 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     m->err.clear();
     if (!grad || (g_obs == nullptr) == (g_bar == nullptr))
         return fail(m, EMM_ERR_ARG, "need grad and exactly one of g_obs, g_bar");
+    if (m->opt.airwave) return fail(m, EMM_ERR_ARG, "the adjoint of the air boundary is not built");
     emm_status st;
     hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
     // forward with checkpoints, unless the last forward stored them for the same acquisition

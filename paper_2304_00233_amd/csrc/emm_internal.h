@@ -21,6 +21,7 @@ struct StepParams {
     int nb;
     // launch decomposition
     int xt, yt, zc, kz;         // x tiles, y tiles, z chunks, planes per chunk
+    int kmin;                   // first updated z plane (r, or the surface node under air)
     int nsrc;
     int nstencil;               // xt * yt * zc * nsrc
     int nrecblk;                // receiver blocks placed first (multiple of 8)

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     const int ty = kScalarRow ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
     const int i0 = bxt * kTileX, j0 = R + byt * TY;
     const int i = i0 + tx, j = j0 + ty;
-    const int k0 = R + bzt * p.kz;
+    const int k0 = p.kmin + bzt * p.kz;
     const int k1 = min(k0 + p.kz, p.n3 - R);
     const bool valid = i >= R && i <= p.n1 - 1 - R && j <= p.n2 - 1 - R;
     const int jc = min(j, p.n2 - 1);

@@ -45,7 +45,7 @@ class emm_options(C.Structure):
                 ("cpml_alpha_max", C.c_double), ("wavelet_fpeak", C.c_double),
                 ("allow_unstable", C.c_int), ("profile", C.c_int), ("tile_kz", C.c_int),
                 ("checkpoint_every", C.c_int), ("graph_steps", C.c_int),
-                ("checkpoint_inner", C.c_int), ("nontemporal", C.c_int)]
+                ("checkpoint_inner", C.c_int), ("nontemporal", C.c_int), ("airwave", C.c_int)]
 
 
 class emm_source(C.Structure):
@@ -266,6 +266,7 @@ def options_for(w, **overrides) -> emm_options:
     o = emm_default_options()
     o.rd, o.nb, o.ne, o.f0, o.cfl = w.rd, w.nb, w.ne, w.f0, w.cfl
     o.nt, o.dft_mode = w.nt, w.dft_mode
+    o.airwave = int(getattr(w, "airwave", False))
     for k, v in overrides.items():
         setattr(o, k, v)
     return o

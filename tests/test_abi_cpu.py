@@ -110,6 +110,14 @@ def test_create_validation_errors(emm):
     # dt above the CFL limit
     st, msg = _create_status(emm, xs, rs, dt_override=1.0)
     assert st == -6 and "stability" in msg
+    # the air boundary: option range, uniform x and y, room for the ghost planes
+    assert _create_status(emm, xs, rs, airwave=2)[0] == -1
+    nu = [x.copy() for x in xs]
+    nu[0][3] += 1.0
+    st, msg = _create_status(emm, nu, rs, airwave=1)
+    assert st == -2 and "uniform" in msg
+    st, msg = _create_status(emm, xs, rs, airwave=1, rd=3, nb=0, ne=2)
+    assert st == -2 and "planes" in msg
 
 
 def test_null_pointers(emm):

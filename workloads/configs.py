@@ -44,6 +44,7 @@ class Workload:
     nt: int = 0                # 0: automatic
     dft_mode: int = 0
     cfl: float = 0.99
+    airwave: bool = False      # air above the first z node (sea surface) instead of an absorbing top
     extra: dict = field(default_factory=dict)
 
     def __post_init__(self):
@@ -125,6 +126,31 @@ def marine_layered(nt: int = 0, box_rho: float = 100.0) -> Workload:
                     sources=np.array([[0.0, 0.0, 950.0]]), receivers=rec,
                     freqs=np.array([0.25, 0.75, 1.25]), rd=2, nb=10, ne=7,
                     f0=1.0, nt=nt)
+
+
+def shallow_marine(nt: int = 0, water_depth: float = 100.0) -> Workload:
+    """Shallow-water marine survey with the air above the sea surface (the
+    paper's air-water top boundary): 128 x 128 x 80 nodes, x and y uniform
+    100 m (the FFTs of the air boundary need it), z from the surface z = 0:
+    16 intervals of 25 m, then 63 intervals growing by 1.05 (~10.9 km).
+    Water 0.3125 ohm-m down to `water_depth`, sediment 1 ohm-m, a 100 ohm-m
+    box 4000 x 4000 x 100 m with its top 1000 m below the seafloor.  One
+    x-dipole 50 m above the seafloor, 101 seafloor receivers, 0.25 / 0.75 /
+    1.25 Hz, r = 2."""
+    x = grids.centred_uniform_axis(128, 100.0)
+    z = grids.axis_from_intervals(0.0, np.concatenate([np.full(16, 25.0),
+                                                       grids.geometric_intervals(25.0, 1.05, 63)]))
+    m = BlockModel(background=1.0)
+    m.add_layer(-np.inf, water_depth, 0.3125)
+    top = water_depth + 1000.0
+    m.add_box(-2000.0, 2000.0, -2000.0, 2000.0, top, top + 100.0, 100.0)
+    r11, r22, r33 = _model_arrays(m, x, x, z)
+    rx = np.arange(-5000.0, 5000.0 + 1, 100.0)
+    rec = np.stack([rx, np.zeros_like(rx), np.full_like(rx, water_depth)], axis=1)
+    return Workload("shallow_marine_air_128x128x80", x, x.copy(), z, r11, r22, r33,
+                    sources=np.array([[0.0, 0.0, water_depth - 50.0]]), receivers=rec,
+                    freqs=np.array([0.25, 0.75, 1.25]), rd=2, nb=10, ne=7, f0=1.0, nt=nt,
+                    airwave=True)
 
 
 def towline_sources(count: int = 16, spacing: float = 500.0, z: float = 950.0):
