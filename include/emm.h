@@ -98,6 +98,13 @@ typedef struct {
                               potential field, E harmonic); needs uniform x and y spacing
                               (EMM_ERR_GRID otherwise); time steps run as direct launches;
                               emm_gradient and emm_forward_batch refuse it (EMM_ERR_ARG) [0] */
+    double converge_tol;   /* > 0: stop early (Section 3.5, Section 4.1) once the lowest-frequency
+                              DTFT of E1 at the 8 corner nodes of the interior changes, between two
+                              checks converge_every steps apart, by at most converge_tol times its
+                              largest corner magnitude, for every source; nt is then the maximum.
+                              With graph_steps, graphs replay only if they divide converge_every.
+                              emm_gradient and emm_forward_batch refuse it [0] */
+    int    converge_every; /* steps between convergence checks [100] */
 } emm_options;
 
 /* A point electric dipole (Section 5, "Survey acquisitions"): position in
@@ -125,6 +132,7 @@ typedef struct {
     int    ckpt_inner;       /* steps between inner checkpoints (== ckpt_outer: one level) */
     double ckpt_bytes;       /* device bytes of checkpoints and per-step E snapshots */
     int    nontemporal;      /* 1: the stencil kernels of the last run used nontemporal hints */
+    int    converged;        /* 1: the last forward stopped at a convergence check (nt = its step) */
 } emm_info;
 
 /* Fill *o with the defaults above. */

@@ -46,6 +46,11 @@ class _Params(C.Structure):
         ("nthreads", C.c_int),
         ("kmin", C.c_int),
         ("ghost", C.c_void_p),
+        ("conv_tol", C.c_double),
+        ("conv_every", C.c_int), ("conv_f", C.c_int),
+        ("corner", _ip),
+        ("nt_done", _ip),
+        ("conv_measure", _dp),
     ]
 
 
@@ -189,15 +194,32 @@ def _build_params(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
     P.nthreads = int(threads or os.cpu_count() or 1)
     P.kmin = r
     P.ghost = None
+    P.conv_tol = 0.0
+    P.conv_every = 1
     keep = (tabs, cp, q, s, ch_arr, rb, rw, phE_re, phE_im, phH_re, phH_im, acc_re, acc_im)
     return P, keep, s
 
 
+def corner_nodes(st: Setup) -> np.ndarray:
+    """(i, j, k) of E1 at the 8 corners of the interior: first and last
+    interior index on each axis (E1's x index i stands for x_{i+1/2})."""
+    n1, n2, n3 = st.n_pad
+    lo = (st.nbe, st.nbe, st.nbe)
+    hi = (n1 - 2 - st.nbe, n2 - 1 - st.nbe, n3 - 1 - st.nbe)
+    return np.array([[hi[a] if c >> a & 1 else lo[a] for a in range(3)] for c in range(8)],
+                    dtype=np.int32)
+
+
 def run_source(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
-               threads: int | None = None, moment: float = 1.0, airwave: bool = False):
+               threads: int | None = None, moment: float = 1.0, airwave: bool = False,
+               converge_tol: float = 0.0, converge_every: int = 100, report: dict | None = None):
     """Time-domain run for one source; returns the receiver DTFT
-    acc[nrec][nchan][nfreq] and the source spectrum S_f.  airwave: the
-    first interior z node is the sea surface with air above it."""
+    acc[nrec][nchan][nfreq] and the source spectrum S_f (over the steps
+    run).  airwave: the first interior z node is the sea surface with air
+    above it.  converge_tol > 0: stop at the first check (every
+    converge_every steps) where the lowest-frequency DTFT of E1 at the
+    interior corners changed by at most converge_tol times its largest
+    magnitude; `report` receives nt_done and the measure at each check."""
     lib = _load()
     P, keep, s = _build_params(st, nt, src, comp, rec, chans, freqs, threads, moment)
     cb = None
@@ -205,12 +227,26 @@ def run_source(st: Setup, nt: int, src, comp: int, rec, chans, freqs,
         cb = _ghost_callback(st)
         P.kmin = st.nbe
         P.ghost = C.cast(cb, C.c_void_p)
+    done = C.c_int(nt)
+    corner = corner_nodes(st)
+    measure = np.zeros(nt // max(1, converge_every) + 1)
+    if converge_tol > 0.0:
+        P.conv_tol = converge_tol
+        P.conv_every = int(converge_every)
+        P.conv_f = int(np.argmin(freqs))
+        P.corner = _ptr(corner, C.c_int)
+        P.nt_done = C.pointer(done)
+        P.conv_measure = _ptr(measure)
     rc = lib.oracle_run(C.byref(P))
     del cb
     if rc < 0:
         raise MemoryError("oracle allocation failed")
+    nd = done.value
+    if report is not None:
+        report["nt_done"] = nd
+        report["measure"] = measure[:nd // max(1, converge_every)].copy()
     acc = keep[-2] + 1j * keep[-1]
-    return acc, T.source_spectrum(s, freqs, st.omega0, st.dt), rc
+    return acc, T.source_spectrum(s[:nd], freqs, st.omega0, st.dt), rc
 
 
 def run_adjoint(st: Setup, nt: int, src, comp: int, rec, chans, freqs, A,
@@ -296,9 +332,12 @@ def green(acc, S, freqs, omega0, chans, moment: float = 1.0):
 
 
 def forward(w, threads: int | None = None, nt: int | None = None,
-            fpeak: float = 0.0, dt_override: float = 0.0):
+            fpeak: float = 0.0, dt_override: float = 0.0, converge_tol: float = 0.0,
+            converge_every: int = 100):
     """Green's functions for every source of workload `w`:
-    complex128 [nsrc][nrec][nchan][nfreq], plus an info dict."""
+    complex128 [nsrc][nrec][nchan][nfreq], plus an info dict.  With
+    converge_tol > 0 each source stops at its own convergence check
+    (info["nt_done"] per source)."""
     freqs = np.asarray(w.freqs, dtype=np.float64)
     fp = T.peak_frequency(freqs, w.f0, fpeak)
     st = make_setup(w, fp, dt_override)
@@ -308,12 +347,17 @@ def forward(w, threads: int | None = None, nt: int | None = None,
     out = np.zeros((len(w.sources), len(w.receivers), len(chans), len(freqs)),
                    dtype=np.complex128)
     nonfinite = False
+    done = []
     for s_i, src in enumerate(w.sources):
+        rep = {}
         acc, S, rc = run_source(st, nt, src, int(w.src_comp[s_i]), w.receivers,
-                                chans, freqs, threads, airwave=w.airwave)
+                                chans, freqs, threads, airwave=w.airwave,
+                                converge_tol=converge_tol, converge_every=converge_every,
+                                report=rep)
         nonfinite |= rc == 1
+        done.append(rep["nt_done"])
         out[s_i] = green(acc, S, freqs, st.omega0, chans)
-    info = dict(dt=st.dt, nt=nt, n_pad=st.n_pad, fp=fp, nonfinite=nonfinite)
+    info = dict(dt=st.dt, nt=nt, n_pad=st.n_pad, fp=fp, nonfinite=nonfinite, nt_done=done)
     return out, info
 
 

@@ -60,6 +60,16 @@ typedef struct {
      * the six fields {E1, E2, E3, H1, H2, H3}; fills the ghost planes above
      * kmin (NULL: none) */
     void (*ghost)(int which, double **fields);
+    /* lowest-frequency convergence stop (conv_tol > 0; Sections 3.5, 4.1):
+     * the DTFT at frequency index conv_f of E1 at 8 corner nodes, compared
+     * every conv_every steps with its value at the previous check; the run
+     * stops once, for the largest corner change d and magnitude a,
+     * 0 < a and d <= conv_tol a */
+    double conv_tol;
+    int conv_every, conv_f;
+    const int *corner;         /* [8][3]: (i, j, k) of E1 */
+    int *nt_done;              /* out: steps run (NULL: not reported) */
+    double *conv_measure;      /* out: d / a at every check made (NULL: not kept) */
 } oracle_params;
 
 #define IDX(k, j, i) (((size_t)(k) * n2 + (size_t)(j)) * n1 + (size_t)(i))
@@ -205,6 +215,8 @@ int oracle_run(const oracle_params *p)
     double *F6[6] = {E1, E2, E3, H1, H2, H3};
     memset(p->acc_re, 0, sizeof(double) * p->nrec * p->nchan * nf);
     memset(p->acc_im, 0, sizeof(double) * p->nrec * p->nchan * nf);
+    double cre[8] = {0}, cim[8] = {0}, pre[8] = {0}, pim[8] = {0};
+    int done = p->nt;
 
     for (int n = 0; n < p->nt; n++) {
         curl_h(p, H1, H2, H3, c1, c2, c3, m, m + N, m + 2 * N, m + 3 * N,
@@ -243,7 +255,31 @@ int oracle_run(const oracle_params *p)
         update(p, H2, NULL, p->ch, c2, -1.0);
         update(p, H3, NULL, p->ch, c3, -1.0);
         if (p->ghost) p->ghost(1, F6);
+        if (p->conv_tol > 0.0) {
+            const size_t ph = (size_t)n * nf + p->conv_f;
+            for (int c = 0; c < 8; c++) {
+                const int *q = p->corner + 3 * c;
+                const double u = E1[IDX(q[2], q[1], q[0])];
+                cre[c] += u * p->phE_re[ph];
+                cim[c] += u * p->phE_im[ph];
+            }
+            if ((n + 1) % p->conv_every == 0) {
+                double d = 0.0, a = 0.0;
+                for (int c = 0; c < 8; c++) {
+                    d = fmax(d, hypot(cre[c] - pre[c], cim[c] - pim[c]));
+                    a = fmax(a, hypot(cre[c], cim[c]));
+                    pre[c] = cre[c];
+                    pim[c] = cim[c];
+                }
+                if (p->conv_measure) p->conv_measure[(n + 1) / p->conv_every - 1] = a > 0.0 ? d / a : 1.0;
+                if (a > 0.0 && d <= p->conv_tol * a) {
+                    done = n + 1;
+                    break;
+                }
+            }
+        }
     }
+    if (p->nt_done) *p->nt_done = done;
     free(buf);
     for (size_t s = 0; s < (size_t)p->nrec * p->nchan * nf; s++)
         if (!isfinite(p->acc_re[s]) || !isfinite(p->acc_im[s])) return 1;

@@ -52,6 +52,10 @@ struct Acq {
     std::vector<float> w_estep, w_hstep;
     emm::StepParams Pe{}, Ph{};
     int ckpt = 0;                                   // checkpoint interval of the stored run (0: none)
+    int nslot = 0;                                  // receiver slots (src, rec, chan)
+    int ncorner = 0;                                // convergence-check slots after them (8 per source)
+    int fmin_index = 0;                             // lowest frequency
+    std::vector<float> wavelet;                     // s_n as stepped (FP32)
     bool valid = false;
 };
 
@@ -194,6 +198,8 @@ emm_status emm_default_options(emm_options *o) {
     o->graph_steps = 0;
     o->checkpoint_inner = 0;
     o->nontemporal = -1;
+    o->converge_tol = 0.0;
+    o->converge_every = 100;
     return EMM_OK;
 }
 
@@ -252,7 +258,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (!(opt.cfl > 0.0) || !std::isfinite(opt.cfl)) return fail(nullptr, EMM_ERR_ARG, "cfl must be > 0");
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
         opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
-        opt.airwave < 0 || opt.airwave > 1 ||
+        opt.airwave < 0 || opt.airwave > 1 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -519,10 +525,35 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
         }
     }
 
+    // convergence check: E1 exactly at the 8 corner nodes of the interior
+    // (first and last interior index per axis; the top ones are the surface
+    // nodes under air), one slot each per source after the receiver slots
+    A.nslot = nsrc * nrec * nch;
+    A.ncorner = m->opt.converge_tol > 0.0 ? 8 * nsrc : 0;
+    if (A.ncorner) {
+        const int lo[3] = {m->nbe, m->nbe, m->nbe};
+        const int hi[3] = {m->np[0] - 2 - m->nbe, m->np[1] - 1 - m->nbe, m->np[2] - 1 - m->nbe};
+        for (int s = 0; s < nsrc; ++s)
+            for (int c = 0; c < 8; ++c) {
+                int base[3];
+                float w[3][2 * emm::kMaxR] = {};
+                for (int a = 0; a < 3; ++a) {
+                    const int idx = (c >> a & 1) ? hi[a] : lo[a];
+                    const int q = idx + L - 1 <= m->np[a] - 1 ? 0 : L - 1;   // keep the stencil in the array
+                    base[a] = idx - q;
+                    w[a][q] = 1.f;
+                }
+                A.items_hstep.insert(A.items_hstep.end(), {s, 0, base[0], base[1], base[2], A.nslot + 8 * s + c});
+                for (int a = 0; a < 3; ++a)
+                    for (int q = 0; q < L; ++q) A.w_hstep.push_back(w[a][q]);
+            }
+    }
+
     // time axis, wavelet, DTFT phases, CPML
     double fmax = 0.0, fmin = 1e300;
     for (int f = 0; f < nfreq; ++f) {
         fmax = std::max(fmax, freq_hz[f]);
+        if (freq_hz[f] < fmin) A.fmin_index = f;
         fmin = std::min(fmin, freq_hz[f]);
     }
     const double fp = m->opt.wavelet_fpeak > 0.0 ? m->opt.wavelet_fpeak : 2.0 * std::sqrt(fmax * m->opt.f0);
@@ -535,6 +566,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     }
     const std::vector<double> sw = emm::wavelet(nt, m->dt, fp);
     std::vector<float> swf(sw.begin(), sw.end());
+    A.wavelet = swf;
     A.Shat.assign(nfreq, 0.0);
     A.wp.assign(nfreq, 0.0);
     std::vector<double2> ph((size_t)2 * nt * nfreq);   // [0]: E-step (H stamps), [1]: H-step (E stamps)
@@ -573,7 +605,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     const long long psys = nb ? (long long)m->np[2] * 2 * nb * m->pitch : 0;
     const long long pszs = nb ? (long long)2 * nb * plane : 0;
     const long long ps_per_src = 4 * (psxs + psys + pszs);      // 2 per axis per half step
-    const int nslot = nsrc * nrec * nch;
+    const int nslot = A.nslot + A.ncorner;
     if ((st = ensure(m, m->fields, (size_t)6 * nsrc * fstride * sizeof(float))) != EMM_OK) return st;
     if ((st = ensure(m, m->psi, (size_t)std::max<long long>(1, nsrc * ps_per_src) * sizeof(float))) != EMM_OK) return st;
     const size_t acc_elem = m->opt.dft_mode ? sizeof(float4) : sizeof(double2);
@@ -839,7 +871,7 @@ emm_status zero_state(emm_model *m, hipStream_t stream) {
     const Acq &A = m->acq;
     const long long fstride = A.Pe.fstride;
     const size_t acc_elem = m->opt.dft_mode ? sizeof(float4) : sizeof(double2);
-    const int nslot = A.nsrc * A.nrec * A.nch;
+    const int nslot = A.nslot + A.ncorner;
     HIP_OK(m, hipMemsetAsync(m->fields.p, 0, (size_t)6 * A.nsrc * fstride * sizeof(float), stream));
     const size_t psi_bytes = (state_floats(m) - 6 * fstride) * A.nsrc * sizeof(float);
     if (psi_bytes) HIP_OK(m, hipMemsetAsync(m->psi.p, 0, psi_bytes, stream));
@@ -912,12 +944,49 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         HIP_OK(m, hipGetLastError());
         return EMM_OK;
     };
+    // convergence stop (converge_tol > 0): every `every` steps, the lowest-
+    // frequency DTFT of E1 at the interior corners against the last check
+    const bool conv = A.ncorner > 0;
+    const int every = m->opt.converge_every;
+    const size_t acc_elem = m->opt.dft_mode ? sizeof(float4) : sizeof(double2);
+    std::vector<std::complex<double>> prev(A.ncorner, 0.0);
+    std::vector<double> craw((size_t)A.ncorner * A.nf * (acc_elem / sizeof(double)));
+    bool converged = false;
+    int n_done = nt;
+    auto check = [&](int nd) -> emm_status {
+        HIP_OK(m, hipMemcpyAsync(craw.data(), (char *)m->acc.p + (size_t)A.nslot * A.nf * acc_elem,
+                                 craw.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIP_OK(m, hipStreamSynchronize(stream));
+        bool all = true;
+        for (int s = 0; s < A.nsrc; ++s) {
+            double num = 0.0, den = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const size_t k = (size_t)(8 * s + c) * A.nf + A.fmin_index;
+                std::complex<double> v;
+                if (m->opt.dft_mode == 0) {
+                    v = {craw[2 * k], craw[2 * k + 1]};
+                } else {
+                    const float *q = reinterpret_cast<const float *>(craw.data()) + 4 * k;
+                    v = {(double)q[0] - (double)q[1], (double)q[2] - (double)q[3]};
+                }
+                num = std::max(num, std::abs(v - prev[8 * s + c]));
+                den = std::max(den, std::abs(v));
+                prev[8 * s + c] = v;
+            }
+            if (!(den > 0.0 && num <= m->opt.converge_tol * den)) all = false;
+        }
+        if (all) {
+            converged = true;
+            n_done = nd;
+        }
+        return EMM_OK;
+    };
     HIP_OK(m, hipEventRecord(m->ev_loop[0], stream));
     int n_begin = 0;
     // K steps per captured hipGraph, replayed with a device step counter;
-    // checkpoints must fall on replay edges
+    // checkpoints and convergence checks must fall on replay edges
     const int K = m->opt.graph_steps;
-    if (K > 0 && nt >= K && (ckpt == 0 || ckpt % K == 0) && !m->opt.airwave) {
+    if (K > 0 && nt >= K && (ckpt == 0 || ckpt % K == 0) && !m->opt.airwave && (!conv || every % K == 0)) {
         if ((st = ensure(m, m->stepdev, 256)) != EMM_OK) return st;
         int *stepd = (int *)m->stepdev.p;
         HIP_OK(m, hipMemsetAsync(stepd, 0, sizeof(int), stream));
@@ -948,15 +1017,33 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
             } else {
                 HIP_OK(m, hipGraphLaunch(exec, stream));
             }
+            if (conv && (n + K) % every == 0) {
+                if ((st = check(n + K)) != EMM_OK) return st;
+                if (converged) break;
+            }
         }
         HIP_OK(m, hipStreamSynchronize(stream));
         (void)hipGraphExecDestroy(exec);
         (void)hipGraphDestroy(graph);
-        n_begin = reps * K;
+        n_begin = converged ? nt : reps * K;
     }
     for (int n = n_begin; n < nt; ++n) {
         if (ckpt > 0 && n % ckpt == 0 && (st = copy_state(m, m->ckpts.p, n / ckpt, true, stream)) != EMM_OK) return st;
         if ((st = step(n, prof && (n - n_begin) % sample == 0)) != EMM_OK) return st;
+        if (conv && (n + 1) % every == 0) {
+            if ((st = check(n + 1)) != EMM_OK) return st;
+            if (converged) break;
+        }
+    }
+    if (converged) {
+        // source spectrum over the steps actually run (same order of sums as
+        // a run of that many steps)
+        for (int f = 0; f < A.nf; ++f) {
+            A.Shat[f] = 0.0;
+            for (int n = 0; n < n_done; ++n)
+                A.Shat[f] += (double)A.wavelet[n] *
+                             std::exp(std::complex<double>(0, 1) * A.wp[f] * ((n + 0.5) * m->dt));
+        }
     }
     HIP_OK(m, hipGetLastError());
     HIP_OK(m, hipEventRecord(m->ev_loop[1], stream));
@@ -966,8 +1053,9 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     HIP_OK(m, hipStreamSynchronize(stream));
     float loop_ms = 0.f;
     HIP_OK(m, hipEventElapsedTime(&loop_ms, m->ev_loop[0], m->ev_loop[1]));
-    A.ckpt = ckpt;
-    m->info.nt = nt;
+    A.ckpt = converged ? 0 : ckpt;
+    m->info.nt = n_done;
+    m->info.converged = converged ? 1 : 0;
     m->info.forward_ms = loop_ms;
     m->info.tile_kz = A.Pe.kz;
     m->info.nontemporal = A.Pe.stream;
@@ -1224,8 +1312,9 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
             return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": a model may appear in one job only");
         if (m->device != jobs[0].model->device)
             return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": all models must be on one device");
-        if (m->opt.airwave)
-            return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) + ": the air boundary runs through emm_forward only");
+        if (m->opt.airwave || m->opt.converge_tol > 0.0)
+            return fail(m, EMM_ERR_ARG, "job " + std::to_string(j) +
+                                            ": the air boundary and the convergence stop run through emm_forward only");
         m->err.clear();
         ms.push_back(m);
     }
@@ -1252,6 +1341,7 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     if (!grad || (g_obs == nullptr) == (g_bar == nullptr))
         return fail(m, EMM_ERR_ARG, "need grad and exactly one of g_obs, g_bar");
     if (m->opt.airwave) return fail(m, EMM_ERR_ARG, "the adjoint of the air boundary is not built");
+    if (m->opt.converge_tol > 0.0) return fail(m, EMM_ERR_ARG, "the gradient needs a fixed step count (converge_tol = 0)");
     emm_status st;
     hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
     // forward with checkpoints, unless the last forward stored them for the same acquisition

@@ -59,7 +59,8 @@ def test_default_options(emm):
     assert (o.rd, o.nb, o.ne, o.f0, o.cfl, o.nt, o.dft_mode) == (2, 10, -1, 1.0, 0.99, 0, 0)
     assert o.cpml_R == 1e-5 and o.cpml_npow == 2.0 and o.profile == 0
     assert (o.checkpoint_every, o.checkpoint_inner, o.graph_steps, o.tile_kz) == (0, 0, 0, 0)
-    assert o.nontemporal == -1
+    assert o.nontemporal == -1 and o.airwave == 0
+    assert o.converge_tol == 0.0 and o.converge_every == 100
 
 
 def test_status_strings(emm):
@@ -110,6 +111,9 @@ def test_create_validation_errors(emm):
     # dt above the CFL limit
     st, msg = _create_status(emm, xs, rs, dt_override=1.0)
     assert st == -6 and "stability" in msg
+    # convergence stop options
+    assert _create_status(emm, xs, rs, converge_tol=-1.0)[0] == -1
+    assert _create_status(emm, xs, rs, converge_every=0)[0] == -1
     # the air boundary: option range, uniform x and y, room for the ghost planes
     assert _create_status(emm, xs, rs, airwave=2)[0] == -1
     nu = [x.copy() for x in xs]

@@ -106,6 +106,24 @@ def test_batched_equals_single_sources(emm):
         assert np.array_equal(Gb[s:s + 1], Gs)
 
 
+def test_convergence_stop_matches_oracle(emm):
+    """The lowest-frequency convergence stop: the GPU stops at the same
+    check as the oracle (measure 1.6e-4 at step 1100, 2.4e-5 at 1200 for
+    tolerance 1e-4), with direct launches and with graphs of 50 steps, and
+    the stopped run equals a fixed run of that many steps bitwise."""
+    w = configs.small_case(seed=61, shape=(24, 22, 20), nb=5, nt=6000, nrec=4, freqs=(0.5, 1.5))
+    G_o, info_o = F.forward(w, converge_tol=1e-4, converge_every=100)
+    for graph in (0, 50):
+        G_g, info = _run(emm, w, converge_tol=1e-4, converge_every=100, graph_steps=graph)
+        assert info["converged"] == 1 and info["nt"] == info_o["nt_done"][0]
+        rep = compare(G_g, G_o, w.channels)
+        print(f"[parity] convergence stop at {info['nt']} (graph {graph}): {rep}", flush=True)
+        assert rep["ok"], rep
+    G_f, info_f = _run(emm, w.with_(nt=info["nt"]))
+    assert info_f["converged"] == 0
+    assert np.array_equal(G_g, G_f)
+
+
 def test_nontemporal_hint_is_bitwise_neutral(emm):
     w = configs.small_case(seed=12, shape=(30, 26, 22), nt=120)
     G0, i0 = _run(emm, w, nontemporal=0)
