@@ -29,6 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # from a 1 GiB copy kernel: 69 207.9 KiB read and 46 142.1 KiB written.  Valid for
 # the kernel as profiled; set to None when the kernel changes until re-measured.
 E_STEP_TRAFFIC_BYTES = (69207.9 * 2.0 + 46142.1 * 1.0) * 1024
+# the same for one launch of the fused step kernel (None until measured)
+LEAP_TRAFFIC_BYTES = None
 
 
 def log(*a):
@@ -166,6 +168,8 @@ def main():
     ap.add_argument("--rd", type=int, default=0, help="override the stencil half length")
     ap.add_argument("--nt", type=int, default=0, help="override the time-step count")
     ap.add_argument("--graph", type=int, default=64, help="time steps per captured hipGraph (0: direct launches)")
+    ap.add_argument("--fused", type=int, default=0, choices=[0, 1],
+                    help="1: one fused launch per time step (E and H updates)")
     ap.add_argument("--tile-kz", type=int, default=-1, help="z planes per block (-1: autotuned)")
     ap.add_argument("--batched", type=int, default=16,
                     help="sources of the batched comparison (0: skip)")
@@ -236,7 +240,7 @@ def main():
         w = w.with_(nt=args.nt)
     log(f"[bench] workload {w.name} padded cells {w.padded_cells}")
 
-    model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz)
+    model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz, fused=args.fused)
     for i in range(args.warmup):
         model.forward()
         log(f"[bench] warmup {i} done")
@@ -261,7 +265,9 @@ def main():
     value = cells * nt * args.steps / wall / 1e9
     e_avg_s = e_ms / e_n / 1e3 if e_n else float("nan")
     h_avg_s = h_ms / h_n / 1e3 if h_n else float("nan")
-    achieved = info["e_bytes"] / e_avg_s / 1e9
+    fused = bool(info["fused"])
+    kbytes = info["leap_bytes"] if fused else info["e_bytes"]
+    achieved = kbytes / e_avg_s / 1e9
     log(f"[bench] nt={nt} wall/forward={ms_per_step:.1f} ms device loop/forward="
         f"{dev_ms / args.steps:.1f} ms e_step avg={e_avg_s * 1e6:.2f} us "
         f"h_step avg={h_avg_s * 1e6:.2f} us tile_kz={info['tile_kz']}")
@@ -275,15 +281,21 @@ def main():
                    "rd": w.rd, "sources": len(w.sources), "receivers": len(w.receivers),
                    "channels": 6, "freqs": [float(f) for f in w.freqs],
                    "step": "one full forward modelling (nt time steps)"},
-        "roofline": {"bound": "hbm", "kernel": "e_step (curl H + CPML + J + E update + H DTFT)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("leap (E update + H update of one step, E on the halo recomputed, "
+                                "J, CPML, DTFT)") if fused else
+                               "e_step (curl H + CPML + J + E update + H DTFT)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": E_STEP_TRAFFIC_BYTES if args.workload == "marine" else None,
-                     "bytes_per_launch": info["e_bytes"], "avg_launch_us": e_avg_s * 1e6},
-        "h_step": {"bytes_per_launch": info["h_bytes"], "avg_launch_us": h_avg_s * 1e6,
-                   "achieved_GBs": info["h_bytes"] / h_avg_s / 1e9},
+                     "traffic": (LEAP_TRAFFIC_BYTES if fused else E_STEP_TRAFFIC_BYTES)
+                     if args.workload == "marine" else None,
+                     "bytes_per_launch": kbytes, "avg_launch_us": e_avg_s * 1e6},
         "device_loop_ms_per_step": dev_ms / args.steps,
+        "fused_step": fused,
     }
+    if not fused:
+        out["h_step"] = {"bytes_per_launch": info["h_bytes"], "avg_launch_us": h_avg_s * 1e6,
+                         "achieved_GBs": info["h_bytes"] / h_avg_s / 1e9}
     if args.batched and args.workload == "marine":
         log(f"[bench] batched comparison with {args.batched} sources")
         out["batched"] = batched_comparison(emm, w, args.batched, args.grad_group, args.grad_ckpt)

@@ -105,6 +105,11 @@ typedef struct {
                               With graph_steps, graphs replay only if they divide converge_every.
                               emm_gradient and emm_forward_batch refuse it [0] */
     int    converge_every; /* steps between convergence checks [100] */
+    int    fused;          /* 1: emm_forward runs one launch per time step (the E update, then
+                              the H update of the same tile, with E recomputed on the x/y halo;
+                              E, H and the E-step CPML memories in ping-pong buffers: 60 instead
+                              of 84 B per cell and step) when no checkpoints, air boundary or
+                              convergence stop are asked for; 0: two half-step launches [0] */
 } emm_options;
 
 /* A point electric dipole (Section 5, "Survey acquisitions"): position in
@@ -133,6 +138,9 @@ typedef struct {
     double ckpt_bytes;       /* device bytes of checkpoints and per-step E snapshots */
     int    nontemporal;      /* 1: the stencil kernels of the last run used nontemporal hints */
     int    converged;        /* 1: the last forward stopped at a convergence check (nt = its step) */
+    int    fused;            /* 1: the last forward ran the fused step kernel; e_kernel_ms,
+                                e_launches then time that kernel and leap_bytes is its traffic */
+    double leap_bytes;       /* algorithmic bytes of one fused step, one source */
 } emm_info;
 
 /* Fill *o with the defaults above. */

@@ -76,6 +76,7 @@ struct emm_model {
     float *tab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // cmx cmy cmz cpx cpy cpz
     // forward-lifetime device data (grown on demand, kept between forwards)
     DevBuf fields, psi, acc, cpml, srcinfo, srcq, wav, items, itemw, phase;
+    DevBuf fieldsB, psiB;                           // second buffers of the fused step (ping-pong)
     DevBuf ckpts;                                   // full-state checkpoints of the last run
     DevBuf ickpts;                                  // inner checkpoints of one outer segment
     DevBuf stepdev;                                 // device step counter of graph replays
@@ -231,7 +232,7 @@ void emm_destroy(emm_model *m) {
     for (float *p : m->ce) if (p) (void)hipFree(p);
     for (float *p : m->tab) if (p) (void)hipFree(p);
     for (DevBuf *b : {&m->fields, &m->psi, &m->acc, &m->cpml, &m->srcinfo, &m->srcq, &m->wav,
-                      &m->items, &m->itemw, &m->phase, &m->ckpts, &m->ickpts, &m->adjf, &m->adjq, &m->adjt,
+                      &m->items, &m->itemw, &m->phase, &m->fieldsB, &m->psiB, &m->ckpts, &m->ickpts, &m->adjf, &m->adjq, &m->adjt,
                       &m->snaps, &m->grad, &m->grad32, &m->tabT, &m->inj, &m->injA, &m->adjcpml, &m->stepdev})
         if (b->p) (void)hipFree(b->p);
     for (hipEvent_t e : m->ev_loop) if (e) (void)hipEventDestroy(e);
@@ -259,6 +260,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
         opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
         opt.airwave < 0 || opt.airwave > 1 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
+        opt.fused < 0 || opt.fused > 1 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -409,6 +411,9 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     m->info.cells = (long long)m->np[0] * m->np[1] * m->np[2];
     step_bytes(m, m->info.e_bytes, m->info.h_bytes);
     m->info.bytes_per_step = m->info.e_bytes + m->info.h_bytes;
+    // fused step: E, H and dt/eps read once, E and H written once (60 B/cell)
+    // plus the same CPML memory traffic as the two half steps
+    m->info.leap_bytes = m->info.bytes_per_step - 24.0 * (double)m->np[0] * m->np[1] * m->np[2];
     *out = m;
     return EMM_OK;
 }
@@ -1059,6 +1064,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     m->info.forward_ms = loop_ms;
     m->info.tile_kz = A.Pe.kz;
     m->info.nontemporal = A.Pe.stream;
+    m->info.fused = 0;
     m->info.e_kernel_ms = prof ? ems : 0.0;
     m->info.h_kernel_ms = prof ? hms : 0.0;
     m->info.e_launches = prof ? nsamp : 0;
@@ -1095,6 +1101,175 @@ std::complex<double> green_factor(const emm_model *m, size_t k) {
     std::complex<double> g = 1.0 / (A.sscale[s] * A.src[s].moment * A.Shat[f]);
     if (A.chans[c] < 3) g *= (2.0 * kPi * A.freqs[f]) / A.wp[f];
     return g;
+}
+
+// All time steps with the fused step kernel: E, H and the E-step CPML
+// memories alternate between two buffers (step n reads set n % 2 and writes
+// the other); the DTFT waves of step n record H^{n+1/2} and E^n, and one last
+// launch without stencil blocks records E^{nt}.
+emm_status leap_loop(emm_model *m, hipStream_t stream) {
+    Acq &A = m->acq;
+    emm_status st;
+    const int nsrc = A.nsrc, nt = A.nt, r = m->r, L = 2 * r;
+    const long long fstride = A.Pe.fstride;
+    if ((st = zero_state(m, stream)) != EMM_OK) return st;
+    const size_t fbytes = (size_t)6 * nsrc * fstride * sizeof(float);
+    const size_t psi_e = (state_floats(m) - 6 * fstride) * nsrc / 2 * sizeof(float);   // E-step half
+    if ((st = ensure(m, m->fieldsB, fbytes)) != EMM_OK) return st;
+    if ((st = ensure(m, m->psiB, std::max<size_t>(psi_e, 256))) != EMM_OK) return st;
+    HIP_OK(m, hipMemsetAsync(m->fieldsB.p, 0, fbytes, stream));
+    if (psi_e) HIP_OK(m, hipMemsetAsync(m->psiB.p, 0, psi_e, stream));
+    // tiling: outputs (65 - 2r) x (rows + 1 - 2r) per block, z chunks of kz
+    emm::LeapParams X{};
+    const int TXO = emm::kTileX - (L - 1), TYO = emm::kLeapRows - (L - 1);
+    X.xt = (m->np[0] - 2 * r + TXO - 1) / TXO;
+    X.yt = (m->np[1] - 2 * r + TYO - 1) / TYO;
+    const int nzv = m->np[2] - 2 * r;
+    X.kz = std::min(std::max(m->opt.tile_kz > 0 ? m->opt.tile_kz : 16, 1), nzv);
+    X.zc = (nzv + X.kz - 1) / X.kz;
+    X.nstencil = X.xt * X.yt * X.zc * nsrc;
+    const int waves = emm::leap_threads() / 64;
+    X.nrech = (int)((A.Pe.nitems + waves - 1) / waves + 7) / 8 * 8;
+    X.nrece = (int)((A.Ph.nitems + waves - 1) / waves + 7) / 8 * 8;
+    // the two parameter sets: parity 0 reads (fields, psi) and writes (fieldsB, psiB)
+    float *FA = (float *)m->fields.p, *FB = (float *)m->fieldsB.p;
+    const size_t cs = (size_t)nsrc * fstride;
+    emm::StepParams pe[2], ph[2];
+    emm::LeapParams xp[2];
+    for (int par = 0; par < 2; ++par) {
+        float *in = par ? FB : FA, *out = par ? FA : FB;
+        pe[par] = A.Pe;
+        ph[par] = A.Ph;
+        for (emm::StepParams *P : {&pe[par], &ph[par]}) {
+            P->E1 = in;
+            P->E2 = in + cs;
+            P->E3 = in + 2 * cs;
+            P->H1 = in + 3 * cs;
+            P->H2 = in + 4 * cs;
+            P->H3 = in + 5 * cs;
+        }
+        xp[par] = X;
+        xp[par].Eo1 = out;
+        xp[par].Eo2 = out + cs;
+        xp[par].Eo3 = out + 2 * cs;
+        xp[par].Ho1 = out + 3 * cs;
+        xp[par].Ho2 = out + 4 * cs;
+        xp[par].Ho3 = out + 5 * cs;
+        // E-step memories: x0 x1 y0 y1 z0 z1 of all sources, in A.Pe's layout
+        float *qa = (float *)m->psi.p, *qb = (float *)m->psiB.p;
+        float *rd_ = par ? qb : qa, *wr_ = par ? qa : qb;
+        auto at = [&](float *base, const float *ref) { return base + (ref - (const float *)m->psi.p); };
+        pe[par].psx0 = at(rd_, A.Pe.psx0);
+        pe[par].psx1 = at(rd_, A.Pe.psx1);
+        pe[par].psy0 = at(rd_, A.Pe.psy0);
+        pe[par].psy1 = at(rd_, A.Pe.psy1);
+        pe[par].psz0 = at(rd_, A.Pe.psz0);
+        pe[par].psz1 = at(rd_, A.Pe.psz1);
+        xp[par].qx0 = at(wr_, A.Pe.psx0);
+        xp[par].qx1 = at(wr_, A.Pe.psx1);
+        xp[par].qy0 = at(wr_, A.Pe.psy0);
+        xp[par].qy1 = at(wr_, A.Pe.psy1);
+        xp[par].qz0 = at(wr_, A.Pe.psz0);
+        xp[par].qz1 = at(wr_, A.Pe.psz1);
+    }
+    const bool prof = m->opt.profile != 0;
+    if (prof && m->ring.empty()) {
+        m->ring.assign(4 * 64, nullptr);
+        for (hipEvent_t &e : m->ring) HIP_OK(m, hipEventCreate(&e));
+    }
+    if (!m->ev_loop[0]) {
+        HIP_OK(m, hipEventCreate(&m->ev_loop[0]));
+        HIP_OK(m, hipEventCreate(&m->ev_loop[1]));
+    }
+    double lms = 0.0;
+    long long nsamp = 0;
+    int used = 0;
+    auto harvest = [&](int slot) -> emm_status {
+        float a = 0.f;
+        HIP_OK(m, hipEventSynchronize(m->ring[2 * slot + 1]));
+        HIP_OK(m, hipEventElapsedTime(&a, m->ring[2 * slot], m->ring[2 * slot + 1]));
+        lms += a;
+        ++nsamp;
+        return EMM_OK;
+    };
+    auto step = [&](int n, bool timed) -> emm_status {
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (timed) {
+            const int slot = used % 128;
+            if (used >= 128) {
+                emm_status s2 = harvest(slot);
+                if (s2 != EMM_OK) return s2;
+            }
+            ++used;
+            t0 = m->ring[2 * slot];
+            t1 = m->ring[2 * slot + 1];
+        }
+        emm::launch_leap(r, pe[n & 1], ph[n & 1], xp[n & 1], n, stream, t0, t1);
+        HIP_OK(m, hipGetLastError());
+        return EMM_OK;
+    };
+    HIP_OK(m, hipEventRecord(m->ev_loop[0], stream));
+    int n_begin = 0;
+    const int K = m->opt.graph_steps;
+    if (K > 0 && K % 2 == 0 && nt >= K) {
+        if ((st = ensure(m, m->stepdev, 256)) != EMM_OK) return st;
+        int *stepd = (int *)m->stepdev.p;
+        HIP_OK(m, hipMemsetAsync(stepd, 0, sizeof(int), stream));
+        emm::StepParams ge[2] = {pe[0], pe[1]}, gh[2] = {ph[0], ph[1]};
+        for (int par = 0; par < 2; ++par) ge[par].step_base = gh[par].step_base = stepd;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_OK(m, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < K; ++j) emm::launch_leap(r, ge[j & 1], gh[j & 1], xp[j & 1], j, stream);
+        emm::launch_advance(stepd, K, stream);
+        HIP_OK(m, hipStreamEndCapture(stream, &graph));
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail(m, EMM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        const int reps = nt / K;
+        for (int q = 0; q < reps; ++q) {
+            if (prof && q % 8 == 0) {
+                for (int j = 0; j < K; ++j)
+                    if ((st = step(q * K + j, j % 4 == 0)) != EMM_OK) return st;
+                emm::launch_advance(stepd, K, stream);
+            } else {
+                HIP_OK(m, hipGraphLaunch(exec, stream));
+            }
+        }
+        HIP_OK(m, hipStreamSynchronize(stream));
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        n_begin = reps * K;
+    }
+    for (int n = n_begin; n < nt; ++n)
+        if ((st = step(n, prof && (n - n_begin) % 16 == 0)) != EMM_OK) return st;
+    // E^{nt}: DTFT waves of the E channels only
+    emm::LeapParams xf = xp[nt & 1];
+    xf.nstencil = 0;
+    xf.nrech = 0;
+    emm::launch_leap(r, pe[nt & 1], ph[nt & 1], xf, nt, stream);
+    HIP_OK(m, hipGetLastError());
+    HIP_OK(m, hipEventRecord(m->ev_loop[1], stream));
+    if (prof)
+        for (int u = std::max(0, used - 128); u < used; ++u)
+            if ((st = harvest(u % 128)) != EMM_OK) return st;
+    HIP_OK(m, hipStreamSynchronize(stream));
+    float loop_ms = 0.f;
+    HIP_OK(m, hipEventElapsedTime(&loop_ms, m->ev_loop[0], m->ev_loop[1]));
+    A.ckpt = 0;
+    m->info.nt = nt;
+    m->info.converged = 0;
+    m->info.fused = 1;
+    m->info.forward_ms = loop_ms;
+    m->info.tile_kz = X.kz;
+    m->info.nontemporal = A.Pe.stream;
+    m->info.e_kernel_ms = prof ? lms : 0.0;
+    m->info.h_kernel_ms = 0.0;
+    m->info.e_launches = prof ? nsamp : 0;
+    m->info.h_launches = 0;
+    return EMM_OK;
 }
 
 // G from the accumulators of the last forward (Section 2.2 normalisation).
@@ -1215,6 +1390,7 @@ emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t
             m->info.forward_ms = ms_loop;
             m->info.tile_kz = m->acq.Pe.kz;
             m->info.nontemporal = m->acq.Pe.stream;
+            m->info.fused = 0;
             m->info.e_kernel_ms = m->info.h_kernel_ms = 0.0;
             m->info.e_launches = m->info.h_launches = 0;
         }
@@ -1296,7 +1472,9 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
     if ((st = prepare(m, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq, stream)) != EMM_OK) return st;
     if ((st = autotune(m, stream)) != EMM_OK) return st;
-    if ((st = time_loop(m, stream, m->opt.checkpoint_every)) != EMM_OK) return st;
+    const bool leap = m->opt.fused && m->opt.checkpoint_every == 0 && !m->opt.airwave &&
+                      !(m->opt.converge_tol > 0.0);
+    if ((st = leap ? leap_loop(m, stream) : time_loop(m, stream, m->opt.checkpoint_every)) != EMM_OK) return st;
     return write_green(m, stream, green);
 }
 

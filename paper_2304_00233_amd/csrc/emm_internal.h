@@ -57,6 +57,24 @@ struct StepParams {
     const int *step_base;
 };
 
+// The fused leap-frog step (one launch per time step): E^{n+1} into new
+// arrays, then H^{n+3/2} into new arrays, with E recomputed on the x/y halo
+// that the H stencil needs.  pe / ph carry the E- and H-step parameters
+// (inputs E^n, H^{n+1/2}; tables; CPML; source; DTFT items of the H and E
+// channels); this struct carries the outputs and the fused tiling.
+constexpr int kLeapRows = 8;   // wavefront rows per block (E region)
+
+struct LeapParams {
+    float *Eo1, *Eo2, *Eo3, *Ho1, *Ho2, *Ho3;   // E^{n+1}, H^{n+3/2} (source 0)
+    float *qx0, *qx1, *qy0, *qy1, *qz0, *qz1;   // E-step CPML memories written (pe.ps* are read)
+    int xt, yt, zc, kz, nstencil;               // tiles of (65 - 2r) x (kLeapRows + 1 - 2r) outputs
+    int nrech, nrece;                           // DTFT blocks: H channels of H^{n+1/2}, E channels of E^n
+};
+
+void launch_leap(int r, const StepParams &pe, const StepParams &ph, const LeapParams &x, int n,
+                 hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+int leap_threads();
+
 // Hardware dispatches workgroup w to XCD w % 8; give every XCD one
 // contiguous range of logical tiles.
 __device__ __forceinline__ int xcd_tile(int w, int total) {

@@ -53,10 +53,10 @@ __device__ __forceinline__ void st1(float *p, float v) {
 // FP64; then acc[f] += u * exp(i w'_f t_n) for every frequency.
 template <int R>
 __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
-                        const float *F1, const float *F2, int n) {
+                        const float *F1, const float *F2, int n, int waves = NT / 64) {
     constexpr int L = 2 * R;
     const int lane = threadIdx.x & 63;
-    const int item = blk * (NT / 64) + (threadIdx.x >> 6);
+    const int item = blk * waves + (threadIdx.x >> 6);
     if (item >= p.nitems) return;
     const int *inf = p.item_info + 6 * item;
     const int s = inf[0], f = inf[1], bx = inf[2], by = inf[3], bz = inf[4], slot = inf[5];
@@ -364,6 +364,358 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
             q1[m] = q1[m + 1];
             q2[m] = q2[m + 1];
         }
+    }
+}
+
+// Fused leap-frog step: one launch per time step reads E^n, H^{n+1/2} and
+// dt/eps once and writes E^{n+1}, H^{n+3/2} to the other buffers of a
+// ping-pong pair (60 B per cell and step instead of 84 for the two half-step
+// kernels).  A block of kLeapRows wavefronts owns an output tile of
+// (65 - 2r) x (kLeapRows + 1 - 2r) columns and a z chunk; it computes
+// E^{n+1} on the 64 x kLeapRows "E region" (the output tile plus the r - 1
+// / r cells of x/y halo the D+ stencil of the H update reaches), plane by
+// plane from z = k0 - r + 1 to k1 + r - 1, keeping the last r + 1 planes in
+// LDS and the last 2r values of E1, E2 of its own column in registers; the
+// H update of plane k - r follows each E plane k.  Every value is the same
+// expression as in the half-step kernels; halo cells' E is computed by
+// several blocks and written only by the owner.  The E-step CPML memories
+// are double-buffered as well (read pe.ps*, write x.q*), because halo cells
+// read the neighbour's memories; the H-step memories stay in place.  The
+// DTFT waves record H^{n+1/2} (stamp (n+1/2) dt) and E^n (stamp n dt, n > 0;
+// E^{nt} is recorded by a last launch with no stencil blocks).
+template <int R, bool ST>
+__global__ __launch_bounds__(kTileX * kLeapRows) void leap_kernel(const StepParams pe, const StepParams ph,
+                                                                 const LeapParams x, int n_arg) {
+    const int n = (pe.step_base ? *pe.step_base : 0) + n_arg;
+    constexpr int TYE = kLeapRows, NTL = kTileX * TYE;
+    constexpr int L = 2 * R;
+    constexpr int W = kTileX + L - 1;         // staged H row length (E-step halo R below, R-1 above)
+    constexpr int HR = TYE + L - 1;           // staged H rows
+    constexpr int TXO = kTileX - (L - 1), TYO = TYE - (L - 1);
+    constexpr int N3 = (HR * W + NTL - 1) / NTL;
+    constexpr int N1 = ((L - 1) * kTileX + NTL - 1) / NTL;
+    __shared__ float sA3[2][HR][W];           // H3: x and y taps of the E update
+    __shared__ float sA2[2][TYE][W];          // H2: x taps
+    __shared__ float sA1[2][HR][kTileX];      // H1: y taps
+    __shared__ float rE1[R + 1][TYE][kTileX]; // E^{n+1} of the last r + 1 planes (H taps)
+    __shared__ float rE2[R + 1][TYE][kTileX];
+    __shared__ float rE3[R + 1][TYE][kTileX];
+
+    const int blk = blockIdx.x;
+    if (blk < x.nrech) {
+        rec_dft<R>(pe, blk, pe.H1, pe.H2, pe.H3, n, TYE);
+        return;
+    }
+    if (blk < x.nrech + x.nrece) {
+        if (n > 0) rec_dft<R>(ph, blk - x.nrech, pe.E1, pe.E2, pe.E3, n - 1, TYE);
+        return;
+    }
+    int t = xcd_tile(blk - x.nrech - x.nrece, x.nstencil);
+    const int s = t % pe.nsrc;
+    t /= pe.nsrc;
+    const int bxt = t % x.xt;
+    t /= x.xt;
+    const int byt = t % x.yt;
+    const int bzt = t / x.yt;
+
+    const int n1 = pe.n1, n2 = pe.n2, n3 = pe.n3, pitch = pe.pitch, plane = (int)pe.plane;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int i0 = R + bxt * TXO - (R - 1), j0 = R + byt * TYO - (R - 1);   // E region origin
+    const int i = i0 + tx, j = j0 + ty;
+    const int k0 = R + bzt * x.kz, k1 = min(k0 + x.kz, n3 - R);
+    const bool ein = i >= R && i <= n1 - 1 - R && j >= R && j <= n2 - 1 - R;   // E cell in the update set
+    const bool own = ein && tx >= R - 1 && tx < R - 1 + TXO && ty >= R - 1 && ty < R - 1 + TYO;
+    const int ic = min(max(i, 0), pitch - 1), jc = min(max(j, 0), n2 - 1);
+    const int ownc = jc * pitch + ic;          // clamped plane offset of this thread's column
+    const long long fo = (long long)s * pe.fstride;
+    const float *H1 = pe.H1 + fo, *H2 = pe.H2 + fo, *H3 = pe.H3 + fo;
+    const float *E1 = pe.E1 + fo, *E2 = pe.E2 + fo, *E3 = pe.E3 + fo;
+    float *Eo1 = x.Eo1 + fo, *Eo2 = x.Eo2 + fo, *Eo3 = x.Eo3 + fo;
+    float *Ho1 = x.Ho1 + fo, *Ho2 = x.Ho2 + fo, *Ho3 = x.Ho3 + fo;
+
+    // tables: D- (E update) and D+ (H update) rows of this column / row
+    const int it = ein ? i : R, jt = ein ? j : R;
+    float cxm[L], cym[L], cxp[L], cyp[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) {
+        cxm[m] = pe.cmx[it * L + m];
+        cym[m] = pe.cmy[jt * L + m];
+        cxp[m] = ph.cpx[it * L + m];
+        cyp[m] = ph.cpy[jt * L + m];
+    }
+    const int nb = pe.nb, nb2 = 2 * nb;
+    const bool xs = ein && (i < nb || i > n1 - 1 - nb);
+    const bool ys = ein && (j < nb || j > n2 - 1 - nb);
+    const int ix = i < nb ? i : i - (n1 - nb2), jy = j < nb ? j : j - (n2 - nb2);
+    float axi = 0.f, bxi = 0.f, ayi = 0.f, byi = 0.f, axh = 0.f, bxh = 0.f, ayh = 0.f, byh = 0.f;
+    if (xs) {
+        axi = pe.axi[i];
+        bxi = pe.bxi[i];
+        axh = ph.axh[i];
+        bxh = ph.bxh[i];
+    }
+    if (ys) {
+        ayi = pe.ayi[j];
+        byi = pe.byi[j];
+        ayh = ph.ayh[j];
+        byh = ph.byh[j];
+    }
+    // E-step memories: read pe.ps*, write x.q* (owner only); H-step memories in place
+    const float *ex0 = pe.psx0 + s * pe.psxs, *ex1 = pe.psx1 + s * pe.psxs;
+    const float *ey0 = pe.psy0 + s * pe.psys, *ey1 = pe.psy1 + s * pe.psys;
+    const float *ez0 = pe.psz0 + s * pe.pszs, *ez1 = pe.psz1 + s * pe.pszs;
+    float *qx0 = x.qx0 + s * pe.psxs, *qx1 = x.qx1 + s * pe.psxs;
+    float *qy0 = x.qy0 + s * pe.psys, *qy1 = x.qy1 + s * pe.psys;
+    float *qz0 = x.qz0 + s * pe.pszs, *qz1 = x.qz1 + s * pe.pszs;
+    float *hx0 = ph.psx0 + s * ph.psxs, *hx1 = ph.psx1 + s * ph.psxs;
+    float *hy0 = ph.psy0 + s * ph.psys, *hy1 = ph.psy1 + s * ph.psys;
+    float *hz0 = ph.psz0 + s * ph.pszs, *hz1 = ph.psz1 + s * ph.pszs;
+
+    const int scomp = pe.src_info[4 * s], sbx = pe.src_info[4 * s + 1], sby = pe.src_info[4 * s + 2],
+              sbz = pe.src_info[4 * s + 3];
+    const float sn = pe.wavelet[n];
+    const float *sq = pe.src_q + (long long)s * L * L * L;
+
+    // staging map of the H planes (as the E step of the half-step kernel)
+    int o3[N3];
+#pragma unroll
+    for (int u = 0; u < N3; ++u) {
+        const int e = tid + u * NTL;
+        const int ly = e / W, lx = e - ly * W;
+        const int gj = j0 - R + ly, gi = i0 - R + lx;
+        o3[u] = (e < HR * W && gj >= 0 && gj < n2 && gi >= 0 && gi < pitch) ? gj * pitch + gi : -1;
+    }
+    auto ly1 = [&](int u) {
+        const int hy = (tid + u * NTL) >> 6;
+        return hy < R ? hy : TYE + hy;
+    };
+    int o1[N1];
+#pragma unroll
+    for (int u = 0; u < N1; ++u) {
+        const int e = tid + u * NTL;
+        const int gj = j0 - R + ly1(u);
+        o1[u] = (e < (L - 1) * kTileX && gj >= 0 && gj < n2 && i >= 0 && i < pitch) ? gj * pitch + i : -1;
+    }
+    int o2 = -1, l2 = -1;
+    if (tid < TYE * (L - 1)) {
+        const int hy = tid / (L - 1), hx = tid % (L - 1);
+        const int lx = hx < R ? hx : kTileX + hx;
+        const int gi = i0 - R + lx, gj = j0 + hy;
+        l2 = hy * W + lx;
+        o2 = (gi >= 0 && gi < pitch && gj >= 0 && gj < n2) ? gj * pitch + gi : -1;
+    }
+    const bool colin = i >= 0 && i < pitch && j >= 0 && j < n2;   // own column inside the array
+
+    const int ka = k0 - R + 1, kb = k1 + R - 1;   // E planes computed
+    // z queues of H1, H2 (E update, planes k-R .. k+R-1) and of E1, E2 (H update)
+    float q1[L], q2[L], g1[L], g2[L];
+    auto hz = [&](const float *A, int kk) -> float {
+        return (colin && kk >= 0 && kk < n3) ? A[(unsigned)(kk * plane + ownc)] : 0.f;
+    };
+#pragma unroll
+    for (int m = 0; m < L; ++m) {
+        g1[m] = 0.f;
+        g2[m] = 0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < L - 1; ++m) {
+        q1[m] = hz(H1, ka - R + m);
+        q2[m] = hz(H2, ka - R + m);
+    }
+    float f3[N3], f1[N1], f2 = 0.f, e1n = 0.f, e2n = 0.f;
+    float un1 = 0.f, un2 = 0.f, un3 = 0.f, cn1 = 0.f, cn2 = 0.f, cn3 = 0.f;
+    auto issue = [&](int k) {
+        const int pk = k * plane;
+#pragma unroll
+        for (int u = 0; u < N3; ++u) f3[u] = o3[u] >= 0 ? H3[(unsigned)(pk + o3[u])] : 0.f;
+#pragma unroll
+        for (int u = 0; u < N1; ++u) f1[u] = o1[u] >= 0 ? H1[(unsigned)(pk + o1[u])] : 0.f;
+        if (o2 >= 0) f2 = H2[(unsigned)(pk + o2)];
+        e1n = hz(H1, k + R - 1);
+        e2n = hz(H2, k + R - 1);
+        if (ein && k >= R && k <= n3 - 1 - R) {
+            const unsigned g = (unsigned)(pk + ownc);
+            un1 = ld1<ST>(&E1[g]);
+            un2 = ld1<ST>(&E2[g]);
+            un3 = ld1<ST>(&E3[g]);
+            cn1 = ld1<ST>(&pe.ce1[g]);
+            cn2 = ld1<ST>(&pe.ce2[g]);
+            cn3 = ld1<ST>(&pe.ce3[g]);
+        }
+    };
+    issue(ka);
+    for (int k = ka; k <= kb; ++k) {
+        const int b = (k - ka) & 1;
+        q1[L - 1] = e1n;
+        q2[L - 1] = e2n;
+        float *s3 = &sA3[b][0][0];
+#pragma unroll
+        for (int u = 0; u < N3; ++u)
+            if (u < N3 - 1 || tid + u * NTL < HR * W) s3[tid + u * NTL] = f3[u];
+        float *s1 = &sA1[b][0][0];
+#pragma unroll
+        for (int u = 0; u < N1; ++u)
+            if (u < N1 - 1 || tid + u * NTL < (L - 1) * kTileX) s1[ly1(u) * kTileX + tx] = f1[u];
+        if (l2 >= 0) (&sA2[b][0][0])[l2] = o2 >= 0 ? f2 : 0.f;
+        sA2[b][ty][tx + R] = q2[R];
+        sA1[b][ty + R][tx] = q1[R];
+        const float u1 = un1, u2 = un2, u3 = un3, ce1 = cn1, ce2 = cn2, ce3 = cn3;
+        __syncthreads();
+        if (k + 1 <= kb) issue(k + 1);
+
+        // ---- E^{n+1} at plane k of the E region
+        float e1 = 0.f, e2 = 0.f, e3 = 0.f;
+        if (ein && k >= R && k <= n3 - 1 - R) {
+            const float *cz = pe.cmz + k * L;
+            float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
+#pragma unroll
+            for (int m = 0; m < L; ++m) {
+                d2a3 += cym[m] * sA3[b][ty + m][tx + R];
+                d2a1 += cym[m] * sA1[b][ty + m][tx];
+                d1a3 += cxm[m] * sA3[b][ty + R][tx + m];
+                d1a2 += cxm[m] * sA2[b][ty][tx + m];
+                d3a2 += cz[m] * q2[m];
+                d3a1 += cz[m] * q1[m];
+            }
+            const bool wr = own && k >= k0 && k < k1;
+            if (xs) {
+                const unsigned id = (unsigned)((k * n2 + j) * nb2 + ix);
+                float v = bxi * ex0[id] + axi * d1a3;
+                if (wr) qx0[id] = v;
+                d1a3 += v;
+                v = bxi * ex1[id] + axi * d1a2;
+                if (wr) qx1[id] = v;
+                d1a2 += v;
+            }
+            if (ys) {
+                const unsigned id = (unsigned)((k * nb2 + jy) * pitch + i);
+                float v = byi * ey0[id] + ayi * d2a3;
+                if (wr) qy0[id] = v;
+                d2a3 += v;
+                v = byi * ey1[id] + ayi * d2a1;
+                if (wr) qy1[id] = v;
+                d2a1 += v;
+            }
+            if (k < nb || k > n3 - 1 - nb) {
+                const int kz = k < nb ? k : k - (n3 - nb2);
+                const float az = pe.azi[k], bz = pe.bzi[k];
+                const unsigned id = (unsigned)((kz * n2 + j) * pitch + i);
+                float v = bz * ez0[id] + az * d3a2;
+                if (wr) qz0[id] = v;
+                d3a2 += v;
+                v = bz * ez1[id] + az * d3a1;
+                if (wr) qz1[id] = v;
+                d3a1 += v;
+            }
+            float c1 = d2a3 - d3a2, c2 = d3a1 - d1a3, c3 = d1a2 - d2a1;
+            if (k >= sbz && k < sbz + L && j >= sby && j < sby + L && i >= sbx && i < sbx + L) {
+                const float jv = sn * sq[((k - sbz) * L + (j - sby)) * L + (i - sbx)];
+                if (scomp == 0) c1 -= jv;
+                else if (scomp == 1) c2 -= jv;
+                else c3 -= jv;
+            }
+            e1 = u1 + ce1 * c1;
+            e2 = u2 + ce2 * c2;
+            e3 = u3 + ce3 * c3;
+            if (wr) {
+                const unsigned g = (unsigned)(k * plane + ownc);
+                st1<ST>(&Eo1[g], e1);
+                st1<ST>(&Eo2[g], e2);
+                st1<ST>(&Eo3[g], e3);
+            }
+        }
+        const int rs = (k - ka) % (R + 1);
+        rE1[rs][ty][tx] = e1;
+        rE2[rs][ty][tx] = e2;
+        rE3[rs][ty][tx] = e3;
+#pragma unroll
+        for (int m = 0; m < L - 1; ++m) {
+            g1[m] = g1[m + 1];
+            g2[m] = g2[m + 1];
+        }
+        g1[L - 1] = e1;
+        g2[L - 1] = e2;
+        __syncthreads();
+
+        // ---- H^{n+3/2} at plane kh = k - R (E planes kh-R+1 .. kh+R are in g1/g2)
+        const int kh = k - R;
+        if (own && kh >= k0 && kh < k1) {
+            const int hs = (kh - ka) % (R + 1);
+            const float *cz = ph.cpz + kh * L;
+            float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
+#pragma unroll
+            for (int m = 0; m < L; ++m) {
+                d2a3 += cyp[m] * rE3[hs][ty - R + 1 + m][tx];
+                d2a1 += cyp[m] * rE1[hs][ty - R + 1 + m][tx];
+                d1a3 += cxp[m] * rE3[hs][ty][tx - R + 1 + m];
+                d1a2 += cxp[m] * rE2[hs][ty][tx - R + 1 + m];
+                d3a2 += cz[m] * g2[m];
+                d3a1 += cz[m] * g1[m];
+            }
+            if (xs) {
+                const unsigned id = (unsigned)((kh * n2 + j) * nb2 + ix);
+                float v = bxh * hx0[id] + axh * d1a3;
+                hx0[id] = v;
+                d1a3 += v;
+                v = bxh * hx1[id] + axh * d1a2;
+                hx1[id] = v;
+                d1a2 += v;
+            }
+            if (ys) {
+                const unsigned id = (unsigned)((kh * nb2 + jy) * pitch + i);
+                float v = byh * hy0[id] + ayh * d2a3;
+                hy0[id] = v;
+                d2a3 += v;
+                v = byh * hy1[id] + ayh * d2a1;
+                hy1[id] = v;
+                d2a1 += v;
+            }
+            if (kh < nb || kh > n3 - 1 - nb) {
+                const int kz = kh < nb ? kh : kh - (n3 - nb2);
+                const float az = ph.azh[kh], bz = ph.bzh[kh];
+                const unsigned id = (unsigned)((kz * n2 + j) * pitch + i);
+                float v = bz * hz0[id] + az * d3a2;
+                hz0[id] = v;
+                d3a2 += v;
+                v = bz * hz1[id] + az * d3a1;
+                hz1[id] = v;
+                d3a1 += v;
+            }
+            const float c1 = d2a3 - d3a2, c2 = d3a1 - d1a3, c3 = d1a2 - d2a1;
+            const unsigned g = (unsigned)(kh * plane + ownc);
+            st1<ST>(&Ho1[g], ld1<ST>(&H1[g]) - ph.ch * c1);
+            st1<ST>(&Ho2[g], ld1<ST>(&H2[g]) - ph.ch * c2);
+            st1<ST>(&Ho3[g], ld1<ST>(&H3[g]) - ph.ch * c3);
+        }
+#pragma unroll
+        for (int m = 0; m < L - 1; ++m) {
+            q1[m] = q1[m + 1];
+            q2[m] = q2[m + 1];
+        }
+    }
+}
+
+int leap_threads() { return kTileX * kLeapRows; }
+
+template <int R, bool ST>
+static void leap_r(const StepParams &pe, const StepParams &ph, const LeapParams &x, int n, hipStream_t s,
+                   hipEvent_t t0, hipEvent_t t1) {
+    const dim3 grid(x.nrech + x.nrece + x.nstencil), block(kTileX * kLeapRows);
+    if (t0 || t1) hipExtLaunchKernelGGL((leap_kernel<R, ST>), grid, block, 0, s, t0, t1, 0, pe, ph, x, n);
+    else hipLaunchKernelGGL((leap_kernel<R, ST>), grid, block, 0, s, pe, ph, x, n);
+}
+
+void launch_leap(int r, const StepParams &pe, const StepParams &ph, const LeapParams &x, int n,
+                 hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    switch (r * 2 + (pe.stream ? 1 : 0)) {
+    case 2: leap_r<1, false>(pe, ph, x, n, s, t0, t1); break;
+    case 3: leap_r<1, true>(pe, ph, x, n, s, t0, t1); break;
+    case 4: leap_r<2, false>(pe, ph, x, n, s, t0, t1); break;
+    case 5: leap_r<2, true>(pe, ph, x, n, s, t0, t1); break;
+    case 6: leap_r<3, false>(pe, ph, x, n, s, t0, t1); break;
+    case 7: leap_r<3, true>(pe, ph, x, n, s, t0, t1); break;
+    case 8: leap_r<4, false>(pe, ph, x, n, s, t0, t1); break;
+    default: leap_r<4, true>(pe, ph, x, n, s, t0, t1); break;
     }
 }
 

@@ -124,6 +124,24 @@ def test_convergence_stop_matches_oracle(emm):
     assert np.array_equal(G_g, G_f)
 
 
+@pytest.mark.parametrize("kw", [dict(seed=70, shape=(37, 29, 23)),
+                                dict(seed=71, rd=1, shape=(70, 13, 11), nb=4),
+                                dict(seed=72, rd=4, shape=(30, 27, 25), nb=5),
+                                dict(seed=73, rd=3, nsrc=3, shape=(33, 31, 24))],
+                         ids=["r2", "r1_ragged", "r4", "r3_three_sources"])
+def test_fused_step_equals_half_steps(emm, kw):
+    """One launch per time step (E recomputed on the halo, ping-pong
+    buffers, lagged E-channel DTFT) gives the two half-step kernels' results
+    bit for bit: direct launches, graph replays and another z chunk."""
+    w = configs.small_case(nt=230, **kw)
+    G0, i0 = _run(emm, w)
+    G1, i1 = _run(emm, w, fused=1)
+    G2, i2 = _run(emm, w, fused=1, graph_steps=16, tile_kz=5)
+    assert (i0["fused"], i1["fused"], i2["fused"]) == (0, 1, 1)
+    assert np.array_equal(G0, G1)
+    assert np.array_equal(G0, G2)
+
+
 def test_nontemporal_hint_is_bitwise_neutral(emm):
     w = configs.small_case(seed=12, shape=(30, 26, 22), nt=120)
     G0, i0 = _run(emm, w, nontemporal=0)
