@@ -132,11 +132,14 @@ def large_fwd_grad(emm, nt: int, group: int, graph: int):
         t = time.perf_counter()
         for s in range(8):
             m.forward(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1])
+            log(f"[bench] large: plain forward of source {s} done")
         out["plain_forward_loop_s"] = time.perf_counter() - t
         m.forward()                                                     # tune for 8 + warm
+        log("[bench] large: batched warm-up done")
         t = time.perf_counter()
         Gb = m.forward()
         out["batched_forward_s"] = time.perf_counter() - t
+        log("[bench] large: batched forward done")
         G_obs = Gb * 1.01
         sched = []
         t = time.perf_counter()
@@ -145,6 +148,7 @@ def large_fwd_grad(emm, nt: int, group: int, graph: int):
             m.gradient(g_obs=G_obs[sl], sources=w.sources[sl], src_comp=w.src_comp[sl])
             i = m.info()
             sched.append([i["ckpt_outer"], i["ckpt_inner"], i["ckpt_bytes"] / 2 ** 30])
+            log(f"[bench] large: gradient of sources {g0}..{sl.stop - 1} done, schedule {sched[-1]}")
         out["forward_gradient_s"] = time.perf_counter() - t
         out["checkpoint_schedule_outer_inner_GiB"] = sched
         out["cells"] = m.info()["cells"]
