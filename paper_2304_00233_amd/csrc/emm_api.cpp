@@ -1403,9 +1403,10 @@ emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t
 
 // Autotuner of the z chunk per thread block and of the nontemporal hint
 // (tile_kz = -1): time a few steps of both stencil kernels for each
-// candidate on this model and acquisition, keep the fastest (cached per
-// source count).  The state it leaves behind is discarded: the time loop
-// starts from zero fields.
+// candidate on this model and acquisition, then time the three fastest
+// again over more steps and keep the best (cached per source count).  The
+// state it leaves behind is discarded: the time loop starts from zero
+// fields.
 emm_status autotune(emm_model *m, hipStream_t stream) {
     Acq &A = m->acq;
     if (m->opt.tile_kz >= 0 || m->tuned.count(A.nsrc)) return EMM_OK;
@@ -1414,46 +1415,55 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     hipEvent_t e0, e1;
     HIP_OK(m, hipEventCreate(&e0));
     HIP_OK(m, hipEventCreate(&e1));
-    float best = 1e30f;
-    int best_kz = A.Pe.kz, best_st = A.Pe.stream;
-    const int steps = 8;
-    for (int st : {0, 1})
-        for (int kz : cand) {
-            if (m->opt.nontemporal >= 0 && st != m->opt.nontemporal) continue;
-            if (kz > nzv) continue;
-            emm::StepParams Pe = A.Pe, Ph = A.Ph;
-            Pe.kz = Ph.kz = kz;
-            Pe.zc = Ph.zc = (nzv + kz - 1) / kz;
-            Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
-            Pe.stream = Ph.stream = st;
-            for (int n = 0; n < 2; ++n) {              // warm-up
-                emm::launch_e_step(m->r, Pe, n, stream);
-                emm::launch_h_step(m->r, Ph, n, stream);
-            }
-            HIP_OK(m, hipEventRecord(e0, stream));
-            for (int n = 0; n < steps; ++n) {
-                emm::launch_e_step(m->r, Pe, n, stream);
-                emm::launch_h_step(m->r, Ph, n, stream);
-            }
-            HIP_OK(m, hipEventRecord(e1, stream));
-            HIP_OK(m, hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_OK(m, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                best_kz = kz;
-                best_st = st;
-            }
+    auto time_it = [&](int kz, int st, int steps, float &ms) -> emm_status {
+        emm::StepParams Pe = A.Pe, Ph = A.Ph;
+        Pe.kz = Ph.kz = kz;
+        Pe.zc = Ph.zc = (nzv + kz - 1) / kz;
+        Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
+        Pe.stream = Ph.stream = st;
+        for (int n = 0; n < 2; ++n) {              // warm-up
+            emm::launch_e_step(m->r, Pe, n, stream);
+            emm::launch_h_step(m->r, Ph, n, stream);
         }
+        HIP_OK(m, hipEventRecord(e0, stream));
+        for (int n = 0; n < steps; ++n) {
+            emm::launch_e_step(m->r, Pe, n, stream);
+            emm::launch_h_step(m->r, Ph, n, stream);
+        }
+        HIP_OK(m, hipEventRecord(e1, stream));
+        HIP_OK(m, hipEventSynchronize(e1));
+        HIP_OK(m, hipEventElapsedTime(&ms, e0, e1));
+        return EMM_OK;
+    };
+    std::vector<std::pair<float, std::pair<int, int>>> first;   // (ms, (kz, stream))
+    emm_status st;
+    for (int sh : {0, 1})
+        for (int kz : cand) {
+            if (kz > nzv || (m->opt.nontemporal >= 0 && sh != m->opt.nontemporal)) continue;
+            float ms = 0.f;
+            if ((st = time_it(kz, sh, 6, ms)) != EMM_OK) return st;
+            first.push_back({ms, {kz, sh}});
+        }
+    std::sort(first.begin(), first.end());
+    float best = 1e30f;
+    std::pair<int, int> pick = first.empty() ? std::make_pair(A.Pe.kz, A.Pe.stream) : first[0].second;
+    for (size_t c = 0; c < std::min<size_t>(3, first.size()); ++c) {
+        float ms = 0.f;
+        if ((st = time_it(first[c].second.first, first[c].second.second, 16, ms)) != EMM_OK) return st;
+        if (ms < best) {
+            best = ms;
+            pick = first[c].second;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_OK(m, hipGetLastError());
-    m->tuned[A.nsrc] = {best_kz, best_st};
+    m->tuned[A.nsrc] = pick;
     for (emm::StepParams *P : {&A.Pe, &A.Ph}) {
-        P->kz = best_kz;
-        P->zc = (nzv + best_kz - 1) / best_kz;
+        P->kz = pick.first;
+        P->zc = (nzv + pick.first - 1) / pick.first;
         P->nstencil = P->xt * P->yt * P->zc * A.nsrc;
-        P->stream = best_st;
+        P->stream = pick.second;
     }
     return EMM_OK;
 }
