@@ -112,7 +112,7 @@ typedef struct {
                               convergence stop are asked for; 0: two half-step launches [0] */
 } emm_options;
 
-/* A point electric dipole (Section 5, "Survey acquisitions"): position in
+/* A point electric dipole (the acquisition of Section 5): position in
  * metres, component 0/1/2 = Jx/Jy/Jz, moment in A.m (G is per unit moment). */
 typedef struct { double x, y, z; int comp; double moment; } emm_source;
 
