@@ -891,7 +891,6 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     Acq &A = m->acq;
     emm_status st;
     const int nsrc = A.nsrc, nt = A.nt, r = m->r;
-    const long long fstride = A.Pe.fstride;
     if ((st = zero_state(m, stream)) != EMM_OK) return st;
     if (ckpt > 0) {
         const int nck = (nt + ckpt - 1) / ckpt;
