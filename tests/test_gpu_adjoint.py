@@ -109,3 +109,18 @@ def test_torch_autograd_function(emm):
     loss.backward()
     assert float(loss) == pytest.approx(chi_ref, rel=1e-9)
     assert np.allclose(ls.grad.numpy(), g_ref, rtol=1e-6, atol=1e-12 * np.max(np.abs(g_ref)))
+
+
+@pytest.mark.slow
+def test_gradient_refuses_a_schedule_that_does_not_fit(emm):
+    """8 sources of the 438 x 438 x 238 grid at 8th order over 18 800 steps
+    need more than 1 TB of checkpoints even with two levels: the planner
+    answers EMM_ERR_OOM (and says to run fewer sources) instead of
+    allocating."""
+    w = configs.large_marine(nt=18800, rd=4, nsrc=8)
+    G = np.ones((8, len(w.receivers), 6, len(w.freqs)), dtype=np.complex128)
+    with emm.Model(w) as m:
+        print("[gpu] gradient planning, large grid, 8 sources", flush=True)
+        with pytest.raises(emm.EmmError) as e:
+            m.gradient(g_obs=G)
+        assert e.value.status == -8 and "fewer sources" in str(e.value)

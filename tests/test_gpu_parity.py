@@ -181,7 +181,9 @@ def test_marine_layered_full_size_vs_stored_oracle(emm):
     g = json.load(open(GOLDEN))
     G_o = (np.array(g["re"]) + 1j * np.array(g["im"])).reshape(g["shape"])
     w = configs.marine_layered(nt=g["nt"])
-    G_g, info = _run(emm, w)
+    # the benchmark's launch configuration: autotuned tiles and hint, 64-step
+    # graph replays, sampled timing launches
+    G_g, info = _run(emm, w, tile_kz=-1, graph_steps=64, profile=1)
     assert info["dt"] == pytest.approx(g["dt"], rel=1e-12)
     rep = compare(G_g, G_o, g["channels"])
     print(f"[parity] marine_layered_128x128x96 full size: {rep}", flush=True)
