@@ -187,8 +187,9 @@ def main():
     ap.add_argument("--large-group", type=int, default=2,
                     help="sources per emm_gradient call of --large-fwd-grad")
     ap.add_argument("--gradient-sample", type=int, default=0, metavar="NT",
-                    help="only run one forward + gradient of the marine workload cut to NT steps "
-                         "(for kernel traces of the adjoint) and exit")
+                    help="only run one forward + gradient of the marine (or, with --workload "
+                         "large, the large-grid) workload cut to NT steps (for kernel traces of "
+                         "the adjoint) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     args = ap.parse_args()
@@ -204,7 +205,10 @@ def main():
     if args.gradient_sample:
         from paper_2304_00233_amd import emm
         from workloads import configs
-        w = configs.marine_layered(nt=args.gradient_sample)
+        if args.workload == "large":
+            w = configs.large_marine(nt=args.gradient_sample, rd=args.rd or 4, nsrc=1)
+        else:
+            w = configs.marine_layered(nt=args.gradient_sample)
         with emm.Model(w, tile_kz=-1, graph_steps=64) as m:
             G = m.forward()
             t = time.perf_counter()
