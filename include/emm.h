@@ -96,8 +96,9 @@ typedef struct {
                               (Section 3.3): no cell above it is updated and the ghost planes the
                               stencils reach are filled after each half step by 2-D FFTs (H as a
                               potential field, E harmonic); needs uniform x and y spacing
-                              (EMM_ERR_GRID otherwise); time steps run as direct launches;
-                              emm_gradient and emm_forward_batch refuse it (EMM_ERR_ARG) [0] */
+                              (EMM_ERR_GRID otherwise); with graph_steps the fills are captured
+                              in the step graphs; emm_gradient and emm_forward_batch refuse it
+                              (EMM_ERR_ARG) [0] */
     double converge_tol;   /* > 0: stop early (Section 3.5, Section 4.1) once the lowest-frequency
                               DTFT of E1 at the 8 corner nodes of the interior changes, between two
                               checks converge_every steps apart, by at most converge_tol times its

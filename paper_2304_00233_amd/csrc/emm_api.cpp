@@ -990,7 +990,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     // K steps per captured hipGraph, replayed with a device step counter;
     // checkpoints and convergence checks must fall on replay edges
     const int K = m->opt.graph_steps;
-    if (K > 0 && nt >= K && (ckpt == 0 || ckpt % K == 0) && !m->opt.airwave && (!conv || every % K == 0)) {
+    if (K > 0 && nt >= K && (ckpt == 0 || ckpt % K == 0) && (!conv || every % K == 0)) {
         if ((st = ensure(m, m->stepdev, 256)) != EMM_OK) return st;
         int *stepd = (int *)m->stepdev.p;
         HIP_OK(m, hipMemsetAsync(stepd, 0, sizeof(int), stream));
@@ -999,12 +999,21 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         HIP_OK(m, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        for (int j = 0; j < K; ++j) {
+        // the air boundary's FFTs and spectral kernels are captured with the steps
+        std::string aerr;
+        bool aok = true;
+        for (int j = 0; j < K && aok; ++j) {
             emm::launch_e_step(r, Pe, j, stream);
+            if (m->air) aok = m->air->fill_E(A.Pe.E1, stream, aerr);
             emm::launch_h_step(r, Ph, j, stream);
+            if (m->air && aok) aok = m->air->fill_H(A.Ph.H1, A.Ph.H3, stream, aerr);
         }
         emm::launch_advance(stepd, K, stream);
-        HIP_OK(m, hipStreamEndCapture(stream, &graph));
+        hipError_t ce = hipStreamEndCapture(stream, &graph);
+        if (!aok || ce != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(m, EMM_ERR_DEVICE, "graph capture: " + (aok ? std::string(hipGetErrorString(ce)) : aerr));
+        }
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             (void)hipGraphDestroy(graph);

@@ -57,6 +57,18 @@ def test_air_boundary_batched_sources_bitwise(emm):
         assert np.array_equal(Gb[s:s + 1], Gs)
 
 
+def test_air_boundary_graph_replays_are_bitwise_identical(emm):
+    """The ghost fills (hipFFT transforms and spectral kernels) captured in
+    the step graphs and replayed 12 times per forward give the direct
+    launches' result bit for bit, twice in a row."""
+    w = _air_case(55, (28, 26, 22), 2, 5, nt=200)
+    G0, i0 = emm.forward_workload(w)
+    with emm.Model(w, graph_steps=16) as m:
+        G1 = m.forward()
+        G2 = m.forward()
+    assert np.array_equal(G0, G1) and np.array_equal(G0, G2)
+
+
 def test_air_boundary_refused_by_gradient_and_batch(emm):
     w = _air_case(54, (21, 20, 19), 2, 4, nt=50)
     with emm.Model(w) as m:
