@@ -100,11 +100,14 @@ emm_status fail(emm_model *m, emm_status s, const std::string &msg) {
     return s;
 }
 
+// HIP failures: out of memory maps to EMM_ERR_OOM, everything else to DEVICE
+emm_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? EMM_ERR_OOM : EMM_ERR_DEVICE; }
+
 #define HIP_OK(m, call)                                                                  \
     do {                                                                                 \
         hipError_t e_ = (call);                                                          \
         if (e_ != hipSuccess)                                                            \
-            return fail((m), EMM_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+            return fail((m), hip_status(e_), std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
 emm_status ensure(emm_model *m, DevBuf &b, size_t bytes) {
@@ -122,6 +125,19 @@ emm_status ensure(emm_model *m, DevBuf &b, size_t bytes) {
     b.bytes = bytes;
     return EMM_OK;
 }
+
+// Owns a captured graph and its executable; destroys them on every exit path.
+struct GraphHold {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GraphHold() = default;
+    GraphHold(const GraphHold &) = delete;
+    GraphHold &operator=(const GraphHold &) = delete;
+    ~GraphHold() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
 
 bool finite_increasing(const double *x, int n) {
     for (int i = 0; i < n; ++i)
@@ -354,11 +370,11 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
         }
 
     // device
-    HIP_OK(m, hipGetDevice(&m->device));
     {
-        hipError_t e = hipStreamCreate(&m->own_stream);
+        hipError_t e = hipGetDevice(&m->device);
+        if (e == hipSuccess) e = hipStreamCreate(&m->own_stream);
         if (e != hipSuccess) {
-            emm_status s = fail(m, EMM_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+            emm_status s = fail(nullptr, EMM_ERR_DEVICE, std::string("device set-up: ") + hipGetErrorString(e));
             delete m;
             return s;
         }
@@ -387,7 +403,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
         hipError_t e = hipMalloc(&m->ce[c3], N * sizeof(float));
         if (e == hipSuccess) e = hipMemcpy(m->ce[c3], buf.data(), N * sizeof(float), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            emm_status s = fail(nullptr, EMM_ERR_DEVICE, std::string("ce upload: ") + hipGetErrorString(e));
+            emm_status s = fail(nullptr, hip_status(e), std::string("ce upload: ") + hipGetErrorString(e));
             emm_destroy(m);
             return s;
         }
@@ -398,7 +414,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
         hipError_t e = hipMalloc(&m->tab[t], f.size() * sizeof(float));
         if (e == hipSuccess) e = hipMemcpy(m->tab[t], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            emm_status s = fail(nullptr, EMM_ERR_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+            emm_status s = fail(nullptr, hip_status(e), std::string("table upload: ") + hipGetErrorString(e));
             emm_destroy(m);
             return s;
         }
@@ -996,8 +1012,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         HIP_OK(m, hipMemsetAsync(stepd, 0, sizeof(int), stream));
         emm::StepParams Pe = A.Pe, Ph = A.Ph;
         Pe.step_base = Ph.step_base = stepd;
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
+        GraphHold gh;
         HIP_OK(m, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         // the air boundary's FFTs and spectral kernels are captured with the steps
         std::string aerr;
@@ -1009,16 +1024,12 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
             if (m->air && aok) aok = m->air->fill_H(A.Ph.H1, A.Ph.H3, stream, aerr);
         }
         emm::launch_advance(stepd, K, stream);
-        hipError_t ce = hipStreamEndCapture(stream, &graph);
-        if (!aok || ce != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
+        hipError_t ce = hipStreamEndCapture(stream, &gh.graph);
+        if (!aok || ce != hipSuccess)
             return fail(m, EMM_ERR_DEVICE, "graph capture: " + (aok ? std::string(hipGetErrorString(ce)) : aerr));
-        }
-        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
+        hipError_t e = hipGraphInstantiate(&gh.exec, gh.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess)
             return fail(m, EMM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        }
         const int reps = nt / K;
         for (int q = 0; q < reps; ++q) {
             const int n = q * K;
@@ -1028,7 +1039,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
                     if ((st = step(n + j, j % 4 == 0)) != EMM_OK) return st;
                 emm::launch_advance(stepd, K, stream);
             } else {
-                HIP_OK(m, hipGraphLaunch(exec, stream));
+                HIP_OK(m, hipGraphLaunch(gh.exec, stream));
             }
             if (conv && (n + K) % every == 0) {
                 if ((st = check(n + K)) != EMM_OK) return st;
@@ -1036,8 +1047,6 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
             }
         }
         HIP_OK(m, hipStreamSynchronize(stream));
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
         n_begin = converged ? nt : reps * K;
     }
     for (int n = n_begin; n < nt; ++n) {
@@ -1225,17 +1234,14 @@ emm_status leap_loop(emm_model *m, hipStream_t stream) {
         HIP_OK(m, hipMemsetAsync(stepd, 0, sizeof(int), stream));
         emm::StepParams ge[2] = {pe[0], pe[1]}, gh[2] = {ph[0], ph[1]};
         for (int par = 0; par < 2; ++par) ge[par].step_base = gh[par].step_base = stepd;
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
+        GraphHold hold;
         HIP_OK(m, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         for (int j = 0; j < K; ++j) emm::launch_leap(r, ge[j & 1], gh[j & 1], xp[j & 1], j, stream);
         emm::launch_advance(stepd, K, stream);
-        HIP_OK(m, hipStreamEndCapture(stream, &graph));
-        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
+        HIP_OK(m, hipStreamEndCapture(stream, &hold.graph));
+        hipError_t e = hipGraphInstantiate(&hold.exec, hold.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess)
             return fail(m, EMM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        }
         const int reps = nt / K;
         for (int q = 0; q < reps; ++q) {
             if (prof && q % 8 == 0) {
@@ -1243,12 +1249,10 @@ emm_status leap_loop(emm_model *m, hipStream_t stream) {
                     if ((st = step(q * K + j, j % 4 == 0)) != EMM_OK) return st;
                 emm::launch_advance(stepd, K, stream);
             } else {
-                HIP_OK(m, hipGraphLaunch(exec, stream));
+                HIP_OK(m, hipGraphLaunch(hold.exec, stream));
             }
         }
         HIP_OK(m, hipStreamSynchronize(stream));
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
         n_begin = reps * K;
     }
     for (int n = n_begin; n < nt; ++n)
