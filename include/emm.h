@@ -111,6 +111,13 @@ typedef struct {
                               E, H and the E-step CPML memories in ping-pong buffers: 60 instead
                               of 84 B per cell and step) when no checkpoints, air boundary or
                               convergence stop are asked for; 0: two half-step launches [0] */
+    int    ce_table;       /* compact dt/eps for the E step: per cell one 32-bit word of three
+                              8-bit indices into a table of the model's distinct FP32 values
+                              (the same values: 4 instead of 12 B per cell), possible when the
+                              three components together hold at most 256 distinct values; then
+                              4 B per padded cell of device memory. -1: used when the autotuner
+                              (tile_kz = -1) measures it faster, else when the arrays of one step
+                              exceed 160 MiB; 1: whenever possible; 0: never [-1] */
 } emm_options;
 
 /* A point electric dipole (the acquisition of Section 5): position in
@@ -126,7 +133,8 @@ typedef struct {
     int    nt;               /* steps of the last forward (or the fixed option; 0 before a forward if automatic) */
     int    n1pad, n2pad, n3pad;
     long long cells;         /* n1pad * n2pad * n3pad */
-    double bytes_per_step;   /* algorithmic HBM bytes of one e-step + h-step, one source */
+    double bytes_per_step;   /* algorithmic HBM bytes of one e-step + h-step, one source, as the
+                                last forward ran them (FP32 dt/eps before the first) */
     double e_bytes, h_bytes; /* split of bytes_per_step over the two stencil kernels */
     /* filled when options.profile = 1: totals over the timed launches of the last forward */
     double e_kernel_ms, h_kernel_ms;   /* summed kernel durations (HIP events) */
@@ -142,6 +150,7 @@ typedef struct {
     int    fused;            /* 1: the last forward ran the fused step kernel; e_kernel_ms,
                                 e_launches then time that kernel and leap_bytes is its traffic */
     double leap_bytes;       /* algorithmic bytes of one fused step, one source */
+    int    ce_table;         /* 1: the last forward's E step read dt/eps in the compact form */
 } emm_info;
 
 /* Fill *o with the defaults above. */

@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,13 @@ struct Acq {
     bool valid = false;
 };
 
+// launch choices the autotuner measured best for one source count
+struct Tune {
+    int kz = 0;        // z planes per block
+    int stream = 0;    // nontemporal hints
+    int compact = 0;   // compact dt/eps in the E step
+};
+
 struct emm_model {
     emm_options opt{};
     int n[3] = {0, 0, 0};     // interior nodes
@@ -73,6 +81,9 @@ struct emm_model {
     hipStream_t own_stream = nullptr;
     // model-lifetime device data
     float *ce[3] = {nullptr, nullptr, nullptr};
+    unsigned *cei = nullptr;  // compact dt/eps of the E step: index words
+    float *cet = nullptr;     //   and the table of distinct values (nullptr: not built)
+    int ncet = 0;
     float *tab[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // cmx cmy cmz cpx cpy cpz
     // forward-lifetime device data (grown on demand, kept between forwards)
     DevBuf fields, psi, acc, cpml, srcinfo, srcq, wav, items, itemw, phase;
@@ -84,7 +95,7 @@ struct emm_model {
     // gradients, transposed tables, injection lists and coefficients
     DevBuf adjf, adjq, adjt, snaps, grad, grad32, tabT, inj, injA, adjcpml;
     Acq acq;
-    std::map<int, std::pair<int, int>> tuned;       // autotuned (z chunk, stream hint) per source count
+    std::map<int, Tune> tuned;                      // autotuned launch choices per source count
     std::unique_ptr<emm::AirBoundary> air;          // ghost planes above the surface (airwave)
     hipEvent_t ev_loop[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ring;       // profiling: start/end pairs
@@ -149,12 +160,14 @@ bool finite_increasing(const double *x, int n) {
 // ce1..3 and writes E1..3 (48 B/cell); H step reads E1..3, H1..3 and writes
 // H1..3 (36 B/cell); each CPML slab cell reads and writes two memory
 // variables per axis per half step (16 B).
-void step_bytes(const emm_model *m, double &eb, double &hb) {
+// E step: E read + written, H read, dt/eps read (3 FP32 arrays, or one
+// index word in the compact form); H step: H read + written, E read
+void step_bytes(const emm_model *m, double &eb, double &hb, bool compact) {
     const double N = double(m->np[0]) * m->np[1] * m->np[2];
     double ncpml = 0.0;
     if (m->nb > 0)
         for (int a = 0; a < 3; ++a) ncpml += 2.0 * m->nb * N / m->np[a];
-    eb = 48.0 * N + 16.0 * ncpml;
+    eb = (compact ? 40.0 : 48.0) * N + 16.0 * ncpml;
     hb = 36.0 * N + 16.0 * ncpml;
 }
 
@@ -168,7 +181,7 @@ int choose_kz(const emm_model *m, int xt, int yt, int nsrc) {
     if (m->opt.tile_kz > 0) return std::min(m->opt.tile_kz, nzv);
     if (m->opt.tile_kz < 0) {
         auto it = m->tuned.find(nsrc);
-        if (it != m->tuned.end()) return it->second.first;
+        if (it != m->tuned.end()) return it->second.kz;
     }
     const long long per_chunk = (long long)xt * yt * nsrc;
     long long zc = std::max<long long>(1, (4096 + per_chunk - 1) / per_chunk);
@@ -183,10 +196,34 @@ int choose_stream(const emm_model *m, long long fstride, int nsrc) {
     if (m->opt.nontemporal >= 0) return m->opt.nontemporal;
     if (m->opt.tile_kz < 0) {
         auto it = m->tuned.find(nsrc);
-        if (it != m->tuned.end()) return it->second.second;
+        if (it != m->tuned.end()) return it->second.stream;
     }
     const double resident = (6.0 * nsrc + 3.0) * (double)fstride * sizeof(float);
     return resident > 160.0 * (1 << 20) ? 1 : 0;
+}
+
+// Compact dt/eps (when the model has it): it saves 8 of the E step's 48 B
+// per cell from HBM, but on a grid whose arrays stay in the Infinity Cache
+// the table lookups cost more than the bytes; same size rule as above,
+// overridden by the autotuner's measurement.
+int choose_compact(const emm_model *m, long long fstride, int nsrc) {
+    if (!m->cei || m->opt.ce_table == 0) return 0;
+    if (m->opt.ce_table == 1) return 1;
+    if (m->opt.tile_kz < 0) {
+        auto it = m->tuned.find(nsrc);
+        if (it != m->tuned.end()) return it->second.compact;
+    }
+    const double resident = (6.0 * nsrc + 3.0) * (double)fstride * sizeof(float);
+    return resident > 160.0 * (1 << 20) ? 1 : 0;
+}
+
+// launch choices of the last run, and the E step's bytes that follow from them
+void note_run(emm_model *m, const emm::StepParams &Pe) {
+    m->info.tile_kz = Pe.kz;
+    m->info.nontemporal = Pe.stream;
+    m->info.ce_table = Pe.cei != nullptr;
+    step_bytes(m, m->info.e_bytes, m->info.h_bytes, Pe.cei != nullptr);
+    m->info.bytes_per_step = m->info.e_bytes + m->info.h_bytes;
 }
 
 }  // namespace
@@ -217,6 +254,7 @@ emm_status emm_default_options(emm_options *o) {
     o->nontemporal = -1;
     o->converge_tol = 0.0;
     o->converge_every = 100;
+    o->ce_table = -1;
     return EMM_OK;
 }
 
@@ -246,6 +284,8 @@ void emm_destroy(emm_model *m) {
     (void)hipSetDevice(m->device);
     if (m->own_stream) (void)hipStreamSynchronize(m->own_stream);
     for (float *p : m->ce) if (p) (void)hipFree(p);
+    if (m->cei) (void)hipFree(m->cei);
+    if (m->cet) (void)hipFree(m->cet);
     for (float *p : m->tab) if (p) (void)hipFree(p);
     for (DevBuf *b : {&m->fields, &m->psi, &m->acc, &m->cpml, &m->srcinfo, &m->srcq, &m->wav,
                       &m->items, &m->itemw, &m->phase, &m->fieldsB, &m->psiB, &m->ckpts, &m->ickpts, &m->adjf, &m->adjq, &m->adjt,
@@ -276,7 +316,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
         opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
         opt.airwave < 0 || opt.airwave > 1 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
-        opt.fused < 0 || opt.fused > 1 ||
+        opt.fused < 0 || opt.fused > 1 || opt.ce_table < -1 || opt.ce_table > 1 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -387,6 +427,13 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     }
     // dt/eps = dt * 2 omega0 rho on the padded grid (rho replicated into the padding)
     std::vector<float> buf(N, 0.0f);
+    // compact form for the E step: the distinct FP32 values of the three
+    // components (at most kCeTable) and per cell their indices, one byte per
+    // component
+    std::vector<unsigned> cidx;
+    std::vector<float> ctab;
+    std::unordered_map<uint32_t, unsigned> code;
+    if (opt.ce_table != 0) cidx.assign(N, 0u);
     for (int c3 = 0; c3 < 3; ++c3) {
         for (int k = 0; k < m->np[2]; ++k) {
             const int kk = std::min(std::max(k - m->nbe, 0), nd[2] - 1);
@@ -400,10 +447,52 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
                 }
             }
         }
+        if (!cidx.empty()) {
+            // cells past n1pad in a row (pitch padding) are never updated: index 0
+            uint32_t last_bits = 0;
+            unsigned last = 0;
+            bool have_last = false;
+            for (int k = 0; k < m->np[2] && !cidx.empty(); ++k)
+                for (int j = 0; j < m->np[1] && !cidx.empty(); ++j) {
+                    const long long row = ((long long)k * m->np[1] + j) * m->pitch;
+                    for (int i = 0; i < m->np[0]; ++i) {
+                        uint32_t bits;
+                        std::memcpy(&bits, &buf[row + i], 4);
+                        if (!have_last || bits != last_bits) {
+                            auto it = code.find(bits);
+                            if (it == code.end()) {
+                                if ((int)code.size() == emm::kCeTable) {
+                                    cidx.clear();    // too many values: FP32 arrays
+                                    break;
+                                }
+                                ctab.push_back(buf[row + i]);
+                                it = code.emplace(bits, (unsigned)code.size()).first;
+                            }
+                            last_bits = bits;
+                            last = it->second;
+                            have_last = true;
+                        }
+                        cidx[row + i] |= last << (8 * c3);
+                    }
+                }
+        }
         hipError_t e = hipMalloc(&m->ce[c3], N * sizeof(float));
         if (e == hipSuccess) e = hipMemcpy(m->ce[c3], buf.data(), N * sizeof(float), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             emm_status s = fail(nullptr, hip_status(e), std::string("ce upload: ") + hipGetErrorString(e));
+            emm_destroy(m);
+            return s;
+        }
+    }
+    if (!cidx.empty()) {
+        hipError_t e = hipMalloc(&m->cei, N * sizeof(unsigned));
+        if (e == hipSuccess) e = hipMemcpy(m->cei, cidx.data(), N * sizeof(unsigned), hipMemcpyHostToDevice);
+        m->ncet = (int)ctab.size();
+        if (e == hipSuccess) e = hipMalloc(&m->cet, ctab.size() * sizeof(float));
+        if (e == hipSuccess)
+            e = hipMemcpy(m->cet, ctab.data(), ctab.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            emm_status s = fail(nullptr, hip_status(e), std::string("ce table upload: ") + hipGetErrorString(e));
             emm_destroy(m);
             return s;
         }
@@ -425,11 +514,13 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     m->info.n2pad = m->np[1];
     m->info.n3pad = m->np[2];
     m->info.cells = (long long)m->np[0] * m->np[1] * m->np[2];
-    step_bytes(m, m->info.e_bytes, m->info.h_bytes);
+    step_bytes(m, m->info.e_bytes, m->info.h_bytes, false);   // until a run chooses
     m->info.bytes_per_step = m->info.e_bytes + m->info.h_bytes;
-    // fused step: E, H and dt/eps read once, E and H written once (60 B/cell)
-    // plus the same CPML memory traffic as the two half steps
-    m->info.leap_bytes = m->info.bytes_per_step - 24.0 * (double)m->np[0] * m->np[1] * m->np[2];
+    // fused step: E, H and dt/eps (FP32 arrays) read once, E and H written
+    // once (60 B/cell) plus the same CPML memory traffic as the two half steps
+    double eb32 = 0.0, hb32 = 0.0;
+    step_bytes(m, eb32, hb32, false);
+    m->info.leap_bytes = eb32 + hb32 - 24.0 * (double)m->np[0] * m->np[1] * m->np[2];
     *out = m;
     return EMM_OK;
 }
@@ -691,6 +782,9 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.ce1 = m->ce[0];
     P.ce2 = m->ce[1];
     P.ce3 = m->ce[2];
+    P.cei = choose_compact(m, fstride, nsrc) ? m->cei : nullptr;
+    P.cet = m->cet;
+    P.ncet = m->ncet;
     P.ch = (float)(m->dt / kMu0);
     P.cmx = m->tab[0];
     P.cmy = m->tab[1];
@@ -1079,8 +1173,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     m->info.nt = n_done;
     m->info.converged = converged ? 1 : 0;
     m->info.forward_ms = loop_ms;
-    m->info.tile_kz = A.Pe.kz;
-    m->info.nontemporal = A.Pe.stream;
+    note_run(m, A.Pe);
     m->info.fused = 0;
     m->info.e_kernel_ms = prof ? ems : 0.0;
     m->info.h_kernel_ms = prof ? hms : 0.0;
@@ -1275,8 +1368,9 @@ emm_status leap_loop(emm_model *m, hipStream_t stream) {
     m->info.converged = 0;
     m->info.fused = 1;
     m->info.forward_ms = loop_ms;
+    note_run(m, A.Pe);
     m->info.tile_kz = X.kz;
-    m->info.nontemporal = A.Pe.stream;
+    m->info.ce_table = 0;                      // the fused kernel reads the FP32 arrays
     m->info.e_kernel_ms = prof ? lms : 0.0;
     m->info.h_kernel_ms = 0.0;
     m->info.e_launches = prof ? nsamp : 0;
@@ -1400,8 +1494,7 @@ emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t
         for (emm_model *m : ms) {
             m->info.nt = m->acq.nt;
             m->info.forward_ms = ms_loop;
-            m->info.tile_kz = m->acq.Pe.kz;
-            m->info.nontemporal = m->acq.Pe.stream;
+            note_run(m, m->acq.Pe);
             m->info.fused = 0;
             m->info.e_kernel_ms = m->info.h_kernel_ms = 0.0;
             m->info.e_launches = m->info.h_launches = 0;
@@ -1424,15 +1517,20 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     if (m->opt.tile_kz >= 0 || m->tuned.count(A.nsrc)) return EMM_OK;
     const int nzv = z_planes(m);
     std::vector<int> cand = {4, 6, 8, 12, 16, 24, 32, 48, 64, A.Pe.kz};
+    std::vector<int> hints = {0, 1}, compacts = {0};
+    if (m->opt.nontemporal >= 0) hints = {m->opt.nontemporal};
+    if (m->cei && m->opt.ce_table == -1) compacts = {0, 1};
+    else if (m->cei && m->opt.ce_table == 1) compacts = {1};
     hipEvent_t e0, e1;
     HIP_OK(m, hipEventCreate(&e0));
     HIP_OK(m, hipEventCreate(&e1));
-    auto time_it = [&](int kz, int st, int steps, float &ms) -> emm_status {
+    auto time_it = [&](const Tune &c, int steps, float &ms) -> emm_status {
         emm::StepParams Pe = A.Pe, Ph = A.Ph;
-        Pe.kz = Ph.kz = kz;
-        Pe.zc = Ph.zc = (nzv + kz - 1) / kz;
+        Pe.kz = Ph.kz = c.kz;
+        Pe.zc = Ph.zc = (nzv + c.kz - 1) / c.kz;
         Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
-        Pe.stream = Ph.stream = st;
+        Pe.stream = Ph.stream = c.stream;
+        Pe.cei = c.compact ? m->cei : nullptr;
         for (int n = 0; n < 2; ++n) {              // warm-up
             emm::launch_e_step(m->r, Pe, n, stream);
             emm::launch_h_step(m->r, Ph, n, stream);
@@ -1447,24 +1545,35 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
         HIP_OK(m, hipEventElapsedTime(&ms, e0, e1));
         return EMM_OK;
     };
-    std::vector<std::pair<float, std::pair<int, int>>> first;   // (ms, (kz, stream))
+    std::vector<std::pair<float, int>> first;   // (ms, index into tried)
+    std::vector<Tune> tried;
     emm_status st;
-    for (int sh : {0, 1})
-        for (int kz : cand) {
-            if (kz > nzv || (m->opt.nontemporal >= 0 && sh != m->opt.nontemporal)) continue;
-            float ms = 0.f;
-            if ((st = time_it(kz, sh, 6, ms)) != EMM_OK) return st;
-            first.push_back({ms, {kz, sh}});
-        }
+    for (int cp : compacts)
+        for (int sh : hints)
+            for (int kz : cand) {
+                if (kz > nzv) continue;
+                Tune c;
+                c.kz = kz;
+                c.stream = sh;
+                c.compact = cp;
+                float ms = 0.f;
+                if ((st = time_it(c, 6, ms)) != EMM_OK) return st;
+                first.push_back({ms, (int)tried.size()});
+                tried.push_back(c);
+            }
     std::sort(first.begin(), first.end());
     float best = 1e30f;
-    std::pair<int, int> pick = first.empty() ? std::make_pair(A.Pe.kz, A.Pe.stream) : first[0].second;
+    Tune pick;
+    pick.kz = A.Pe.kz;
+    pick.stream = A.Pe.stream;
+    pick.compact = A.Pe.cei != nullptr;
+    if (!first.empty()) pick = tried[first[0].second];
     for (size_t c = 0; c < std::min<size_t>(3, first.size()); ++c) {
         float ms = 0.f;
-        if ((st = time_it(first[c].second.first, first[c].second.second, 16, ms)) != EMM_OK) return st;
+        if ((st = time_it(tried[first[c].second], 16, ms)) != EMM_OK) return st;
         if (ms < best) {
             best = ms;
-            pick = first[c].second;
+            pick = tried[first[c].second];
         }
     }
     (void)hipEventDestroy(e0);
@@ -1472,11 +1581,12 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     HIP_OK(m, hipGetLastError());
     m->tuned[A.nsrc] = pick;
     for (emm::StepParams *P : {&A.Pe, &A.Ph}) {
-        P->kz = pick.first;
-        P->zc = (nzv + pick.first - 1) / pick.first;
+        P->kz = pick.kz;
+        P->zc = (nzv + pick.kz - 1) / pick.kz;
         P->nstencil = P->xt * P->yt * P->zc * A.nsrc;
-        P->stream = pick.second;
+        P->stream = pick.stream;
     }
+    A.Pe.cei = pick.compact ? m->cei : nullptr;
     return EMM_OK;
 }
 

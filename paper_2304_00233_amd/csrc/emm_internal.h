@@ -11,6 +11,7 @@ namespace emm {
 constexpr int kTileX = 64;     // one wavefront row along x (wave64)
 constexpr int kMaxR = 4;       // 8th order in space at most
 constexpr int kTileY = 4;      // rows (wavefronts) per thread block
+constexpr int kCeTable = 256;  // distinct dt/eps values of a model in the compact form
 
 // Everything one half-step kernel needs; passed by value.
 struct StepParams {
@@ -30,6 +31,13 @@ struct StepParams {
     float *E1, *E2, *E3, *H1, *H2, *H3;
     float *Eo1, *Eo2, *Eo3;          // where the E step writes E (== E1..3: in place)
     const float *ce1, *ce2, *ce3;   // dt/eps at Ex/Ey/Ez positions
+    // Optional compact dt/eps for the E step (nullptr: read ce1..3): per cell
+    // one word whose bytes 0, 1, 2 index the Ex, Ey, Ez values in cet, the
+    // table of the ncet (<= kCeTable) distinct dt/eps values of the model
+    // (exact: the same FP32 values)
+    const unsigned *cei;
+    const float *cet;
+    int ncet;
     float ch;                        // dt/mu0
     // FD tables [n_d][2R]: cm = D- at integer nodes, cp = D+ at half nodes
     const float *cmx, *cmy, *cmz, *cpx, *cpy, *cpz;

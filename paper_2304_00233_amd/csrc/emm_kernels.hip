@@ -37,8 +37,8 @@ constexpr int NT = kTileX * TY;
 
 int block_threads() { return NT; }
 
-template <bool ST>
-__device__ __forceinline__ float ld1(const float *p) {
+template <bool ST, typename T>
+__device__ __forceinline__ T ld1(const T *p) {
     if constexpr (ST) return __builtin_nontemporal_load(p);
     else return *p;
 }
@@ -107,7 +107,11 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
 // loads are in flight.  Two LDS buffers make one barrier per plane enough: a
 // buffer is rewritten only after every wave has passed the barrier that
 // follows its last use.
-template <int R, bool HS, bool ST>
+//
+// CI (E step only): dt/eps comes from the compact form, one index word per
+// cell (4 bytes instead of 12) into a table of the model's distinct values,
+// held in LDS.
+template <int R, bool HS, bool ST, bool CI>
 __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg) {
     const int n = (p.step_base ? *p.step_base : 0) + n_arg;
     constexpr int L = 2 * R;
@@ -119,6 +123,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     __shared__ float sA3[2][HR][W];           // x and y taps
     __shared__ float sA2[2][TY][W];           // x taps
     __shared__ float sA1[2][HR][kTileX];      // y taps
+    __shared__ float sCe[CI ? kCeTable : 1];
+    static_assert(kCeTable <= NT, "one table entry per thread");
 
     const float *A1 = HS ? p.E1 : p.H1;
     const float *A2 = HS ? p.E2 : p.H2;
@@ -198,6 +204,8 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     float *py0 = p.psy0 + s * p.psys, *py1 = p.psy1 + s * p.psys;
     float *pz0 = p.psz0 + s * p.pszs, *pz1 = p.psz1 + s * p.pszs;
     const float *ce1 = p.ce1, *ce2 = p.ce2, *ce3 = p.ce3;
+    // read only after the first barrier of the plane loop
+    if (CI && (int)threadIdx.x < p.ncet) sCe[threadIdx.x] = p.cet[threadIdx.x];
 
     // dipole source of this block's source (E step only)
     int scomp = -1, sbx = 0, sby = 0, sbz = 0;
@@ -257,6 +265,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     // staged registers of the next plane
     float f3[N3], f1[N1], f2 = 0.f, e1n, e2n;
     float un1 = 0.f, un2 = 0.f, un3 = 0.f, cn1 = 0.f, cn2 = 0.f, cn3 = 0.f;
+    unsigned cin = 0;
     auto issue = [&](int k) {
         const int pk = k * plane;
 #pragma unroll
@@ -272,7 +281,9 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
             un1 = ld1<ST>(&U1[g]);
             un2 = ld1<ST>(&U2[g]);
             un3 = ld1<ST>(&U3[g]);
-            if (!HS) {
+            if (!HS && CI) {
+                cin = ld1<ST>(&p.cei[g]);
+            } else if (!HS) {
                 cn1 = ld1<ST>(&ce1[g]);
                 cn2 = ld1<ST>(&ce2[g]);
                 cn3 = ld1<ST>(&ce3[g]);
@@ -296,9 +307,16 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         if (l2 >= 0) (&sA2[b][0][0])[l2] = o2 >= 0 ? f2 : 0.f;
         sA2[b][ty][tx + HL] = q2[HL];
         sA1[b][ty + HL][tx] = q1[HL];
-        const float u1 = un1, u2 = un2, u3 = un3, ce1 = cn1, ce2 = cn2, ce3 = cn3;
+        const float u1 = un1, u2 = un2, u3 = un3;
+        float ce1 = cn1, ce2 = cn2, ce3 = cn3;
+        const unsigned ci = cin;
         __syncthreads();
         if (k + 1 < k1) issue(k + 1);
+        if (CI) {
+            ce1 = sCe[ci & 255u];
+            ce2 = sCe[(ci >> 8) & 255u];
+            ce3 = sCe[(ci >> 16) & 255u];
+        }
 
         if (valid) {
             const float *cz = tz_ + k * L;
@@ -719,26 +737,31 @@ void launch_leap(int r, const StepParams &pe, const StepParams &ph, const LeapPa
     }
 }
 
-template <int R, bool HS, bool ST>
+template <int R, bool HS, bool ST, bool CI>
 static void launch_r(const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const dim3 grid(p.nrecblk + p.nstencil), block(NT);
-    if (t0 || t1) hipExtLaunchKernelGGL((step_kernel<R, HS, ST>), grid, block, 0, s, t0, t1, 0, p, n);
-    else hipLaunchKernelGGL((step_kernel<R, HS, ST>), grid, block, 0, s, p, n);
+    if (t0 || t1) hipExtLaunchKernelGGL((step_kernel<R, HS, ST, CI>), grid, block, 0, s, t0, t1, 0, p, n);
+    else hipLaunchKernelGGL((step_kernel<R, HS, ST, CI>), grid, block, 0, s, p, n);
 }
 
-template <bool HS, bool ST>
+template <bool HS, bool ST, bool CI>
 static void launch(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     switch (r) {
-    case 1: launch_r<1, HS, ST>(p, n, s, t0, t1); break;
-    case 2: launch_r<2, HS, ST>(p, n, s, t0, t1); break;
-    case 3: launch_r<3, HS, ST>(p, n, s, t0, t1); break;
-    default: launch_r<4, HS, ST>(p, n, s, t0, t1); break;
+    case 1: launch_r<1, HS, ST, CI>(p, n, s, t0, t1); break;
+    case 2: launch_r<2, HS, ST, CI>(p, n, s, t0, t1); break;
+    case 3: launch_r<3, HS, ST, CI>(p, n, s, t0, t1); break;
+    default: launch_r<4, HS, ST, CI>(p, n, s, t0, t1); break;
     }
 }
 
 void launch_e_step(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    if (p.stream) launch<false, true>(r, p, n, s, t0, t1);
-    else launch<false, false>(r, p, n, s, t0, t1);
+    if (p.cei) {
+        if (p.stream) launch<false, true, true>(r, p, n, s, t0, t1);
+        else launch<false, false, true>(r, p, n, s, t0, t1);
+    } else {
+        if (p.stream) launch<false, true, false>(r, p, n, s, t0, t1);
+        else launch<false, false, false>(r, p, n, s, t0, t1);
+    }
 }
 
 // graph replays: advance the device step counter by k after each replay
@@ -750,8 +773,8 @@ void launch_advance(int *step, int k, hipStream_t s) {
     hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, step, k);
 }
 void launch_h_step(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    if (p.stream) launch<true, true>(r, p, n, s, t0, t1);
-    else launch<true, false>(r, p, n, s, t0, t1);
+    if (p.stream) launch<true, true, false>(r, p, n, s, t0, t1);
+    else launch<true, false, false>(r, p, n, s, t0, t1);
 }
 
 }  // namespace emm

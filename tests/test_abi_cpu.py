@@ -61,6 +61,7 @@ def test_default_options(emm):
     assert (o.checkpoint_every, o.checkpoint_inner, o.graph_steps, o.tile_kz) == (0, 0, 0, 0)
     assert o.nontemporal == -1 and o.airwave == 0
     assert o.converge_tol == 0.0 and o.converge_every == 100
+    assert o.fused == 0 and o.ce_table == -1
 
 
 def test_status_strings(emm):
@@ -114,6 +115,9 @@ def test_create_validation_errors(emm):
     # convergence stop options
     assert _create_status(emm, xs, rs, converge_tol=-1.0)[0] == -1
     assert _create_status(emm, xs, rs, converge_every=0)[0] == -1
+    # compact dt/eps: automatic (-1), off (0) or whenever possible (1)
+    assert _create_status(emm, xs, rs, ce_table=2)[0] == -1
+    assert _create_status(emm, xs, rs, ce_table=-2)[0] == -1
     # the air boundary: option range, uniform x and y, room for the ghost planes
     assert _create_status(emm, xs, rs, airwave=2)[0] == -1
     nu = [x.copy() for x in xs]

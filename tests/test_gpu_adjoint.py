@@ -84,6 +84,21 @@ def test_checkpoint_schedules_and_reuse_are_bitwise(emm):
         assert np.array_equal(g1, g) and c1 == c
 
 
+def test_compact_dt_eps_gradient_is_bitwise(emm):
+    """The forward and the recomputation inside emm_gradient reading dt/eps
+    in the compact form give the FP32 arrays' gradient bit for bit."""
+    w, wo = _case(seed=38, nt=180)
+    G_obs, _ = F.forward(wo)
+    with emm.Model(w, ce_table=0) as m:
+        g0, _, c0 = m.gradient(g_obs=G_obs)
+        i0 = m.info()
+    with emm.Model(w, ce_table=1) as m:
+        g1, _, c1 = m.gradient(g_obs=G_obs)
+        i1 = m.info()
+    assert (i0["ce_table"], i1["ce_table"]) == (0, 1)
+    assert np.array_equal(g0, g1) and c0 == c1
+
+
 def test_cotangent_entry_equals_misfit_entry(emm):
     w, wo = _case(seed=37, nt=200)
     G_obs, _ = F.forward(wo)
