@@ -1508,15 +1508,25 @@ emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t
 
 // Autotuner of the z chunk per thread block and of the nontemporal hint
 // (tile_kz = -1): time a few steps of both stencil kernels for each
-// candidate on this model and acquisition, then time the three fastest
-// again over more steps and keep the best (cached per source count).  The
+// candidate (z planes per block x nontemporal hint x compact dt/eps) on this
+// model and acquisition, then time the four fastest again over more steps
+// and keep the best (cached per source count).  The
 // state it leaves behind is discarded: the time loop starts from zero
 // fields.
 emm_status autotune(emm_model *m, hipStream_t stream) {
     Acq &A = m->acq;
     if (m->opt.tile_kz >= 0 || m->tuned.count(A.nsrc)) return EMM_OK;
     const int nzv = z_planes(m);
-    std::vector<int> cand = {4, 6, 8, 12, 16, 24, 32, 48, 64, A.Pe.kz};
+    // every distinct z chunking with 3..64 planes per block (the smallest kz
+    // of each chunk count): how many waves of blocks a launch needs on the
+    // chip moves the time by several per cent between neighbouring kz
+    std::vector<int> cand;
+    for (int zc = 1; zc <= nzv; ++zc) {
+        const int kz = (nzv + zc - 1) / zc;
+        if (kz < 3) break;
+        if (kz <= 64 && (cand.empty() || cand.back() != kz)) cand.push_back(kz);
+    }
+    if (std::find(cand.begin(), cand.end(), A.Pe.kz) == cand.end()) cand.push_back(A.Pe.kz);
     std::vector<int> hints = {0, 1}, compacts = {0};
     if (m->opt.nontemporal >= 0) hints = {m->opt.nontemporal};
     if (m->cei && m->opt.ce_table == -1) compacts = {0, 1};
@@ -1551,7 +1561,6 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     for (int cp : compacts)
         for (int sh : hints)
             for (int kz : cand) {
-                if (kz > nzv) continue;
                 Tune c;
                 c.kz = kz;
                 c.stream = sh;
@@ -1568,7 +1577,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     pick.stream = A.Pe.stream;
     pick.compact = A.Pe.cei != nullptr;
     if (!first.empty()) pick = tried[first[0].second];
-    for (size_t c = 0; c < std::min<size_t>(3, first.size()); ++c) {
+    for (size_t c = 0; c < std::min<size_t>(4, first.size()); ++c) {
         float ms = 0.f;
         if ((st = time_it(tried[first[c].second], 16, ms)) != EMM_OK) return st;
         if (ms < best) {
