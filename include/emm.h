@@ -115,9 +115,15 @@ typedef struct {
                               8-bit indices into a table of the model's distinct FP32 values
                               (the same values: 4 instead of 12 B per cell), possible when the
                               three components together hold at most 256 distinct values; then
-                              4 B per padded cell of device memory. -1: used when the autotuner
-                              (tile_kz = -1) measures it faster, else when the arrays of one step
-                              exceed 160 MiB; 1: whenever possible; 0: never [-1] */
+                              4 B per padded cell of device memory. -1: used whenever possible
+                              unless the autotuner (tile_kz = -1) measures the FP32 arrays
+                              faster; 1: whenever possible; 0: never [-1] */
+    int    src_group;      /* sources per time loop of emm_forward, which runs the loops one after
+                              another (results are the same bit for bit): 0 = as many as keep the
+                              arrays of one step within 160 MiB, so they stay in the 256 MB
+                              Infinity Cache between steps, or all when one source alone does
+                              not fit; -1 = all; k > 0 = k. With checkpoint_every or converge_tol
+                              set, all sources run in one loop [0] */
 } emm_options;
 
 /* A point electric dipole (the acquisition of Section 5): position in
@@ -151,6 +157,8 @@ typedef struct {
                                 e_launches then time that kernel and leap_bytes is its traffic */
     double leap_bytes;       /* algorithmic bytes of one fused step, one source */
     int    ce_table;         /* 1: the last forward's E step read dt/eps in the compact form */
+    int    src_group;        /* sources per time loop of the last emm_forward (jobs per graph
+                                after emm_forward_batch) */
 } emm_info;
 
 /* Fill *o with the defaults above. */
@@ -205,7 +213,13 @@ typedef struct {
  * sources share one launch stream).  When a job has done all its whole
  * graph_steps blocks, the graph is captured again without it and its last
  * nt % graph_steps steps run as direct launches.  Each job's green is
- * exactly what emm_forward writes for it (bitwise).  A model may appear in
+ * exactly what emm_forward writes for it (bitwise).  Jobs run in
+ * consecutive groups, one graph per group, group after group, by the
+ * src_group option of the first job's model: -1 = all jobs in one graph,
+ * k > 0 = k jobs per graph, 0 = as many jobs as keep their arrays within
+ * 160 MiB (the Infinity Cache rule of emm_forward; a job that alone exceeds
+ * it runs by itself); info.src_group of each model then holds the number of
+ * jobs in its graph.  A model may appear in
  * one job only; every model must live on the same device.  hip_stream: as
  * emm_forward (NULL = the first model's stream).  Errors: as emm_forward;
  * the first failing job stops the call (emm_last_error of that model). */

@@ -202,19 +202,16 @@ int choose_stream(const emm_model *m, long long fstride, int nsrc) {
     return resident > 160.0 * (1 << 20) ? 1 : 0;
 }
 
-// Compact dt/eps (when the model has it): it saves 8 of the E step's 48 B
-// per cell from HBM, but on a grid whose arrays stay in the Infinity Cache
-// the table lookups cost more than the bytes; same size rule as above,
-// overridden by the autotuner's measurement.
-int choose_compact(const emm_model *m, long long fstride, int nsrc) {
+// Compact dt/eps whenever the model has it (8 of the E step's 48 B per
+// cell less; measured faster on grids in and beyond the Infinity Cache),
+// unless the autotuner measured the FP32 arrays faster.
+int choose_compact(const emm_model *m, int nsrc) {
     if (!m->cei || m->opt.ce_table == 0) return 0;
-    if (m->opt.ce_table == 1) return 1;
-    if (m->opt.tile_kz < 0) {
+    if (m->opt.ce_table == -1 && m->opt.tile_kz < 0) {
         auto it = m->tuned.find(nsrc);
         if (it != m->tuned.end()) return it->second.compact;
     }
-    const double resident = (6.0 * nsrc + 3.0) * (double)fstride * sizeof(float);
-    return resident > 160.0 * (1 << 20) ? 1 : 0;
+    return 1;
 }
 
 // launch choices of the last run, and the E step's bytes that follow from them
@@ -255,6 +252,7 @@ emm_status emm_default_options(emm_options *o) {
     o->converge_tol = 0.0;
     o->converge_every = 100;
     o->ce_table = -1;
+    o->src_group = 0;
     return EMM_OK;
 }
 
@@ -316,7 +314,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
         opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
         opt.airwave < 0 || opt.airwave > 1 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
-        opt.fused < 0 || opt.fused > 1 || opt.ce_table < -1 || opt.ce_table > 1 ||
+        opt.fused < 0 || opt.fused > 1 || opt.ce_table < -1 || opt.ce_table > 1 || opt.src_group < -1 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -550,6 +548,49 @@ bool same_acquisition(const Acq &a, const emm_source *src, int nsrc, const emm_r
 // Validate the acquisition, build the host tables (stencils, wavelet, DTFT
 // phases, CPML), upload them and fill the kernel parameters (Sections 3.1,
 // 3.4, 3.5; see emm_forward in emm.h).
+// A source's component, moment and position: its (2r)^3 stencil on the grid
+// of its E component must lie inside the interior.
+emm_status check_source(emm_model *m, const emm_source &S) {
+    if (S.comp < 0 || S.comp > 2 || !std::isfinite(S.moment) || S.moment == 0.0 || !std::isfinite(S.x) ||
+        !std::isfinite(S.y) || !std::isfinite(S.z))
+        return fail(m, EMM_ERR_ARG, "source component must be 0..2 with a finite non-zero moment");
+    const double p[3] = {S.x, S.y, S.z};
+    const int L = 2 * m->r;
+    for (int a = 0; a < 3; ++a) {
+        double w[2 * emm::kMaxR];
+        const int base = emm::point_stencil(a == S.comp ? m->half[a] : m->axes[a], p[a], m->r, w);
+        if (!(base >= m->nbe && base + L - 1 <= m->np[a] - 1 - m->nbe))
+            return fail(m, EMM_ERR_GEOMETRY, "source stencil leaves the interior");
+    }
+    return EMM_OK;
+}
+
+// bytes of one source's full time-stepping state (fields + CPML memories)
+size_t state_floats(const emm_model *m) {
+    const long long plane = (long long)m->pitch * m->np[1];
+    const long long fstride = plane * m->np[2];
+    const int nb = m->nb;
+    const long long psxs = nb ? (long long)m->np[2] * m->np[1] * 2 * nb : 0;
+    const long long psys = nb ? (long long)m->np[2] * 2 * nb * m->pitch : 0;
+    const long long pszs = nb ? (long long)2 * nb * plane : 0;
+    return (size_t)(6 * fstride + 4 * (psxs + psys + pszs));
+}
+
+// Sources per time loop of emm_forward: the src_group option, else (0) as
+// many as keep the arrays of one step within 160 MiB, so that they stay in
+// the 256 MB Infinity Cache from step to step (batching sources on such a
+// grid measured slower than one source after another), or all of them when
+// one source alone does not fit.
+int source_group(const emm_model *m, int nsrc) {
+    if (m->opt.src_group > 0) return std::min(m->opt.src_group, nsrc);
+    if (m->opt.src_group < 0) return nsrc;
+    const double budget = 160.0 * (1 << 20);
+    const double per = 4.0 * (double)state_floats(m);
+    const double shared = (double)m->pitch * m->np[1] * m->np[2] * (m->cei ? 4.0 : 12.0);
+    if (per + shared > budget) return nsrc;
+    return std::max(1, std::min(nsrc, (int)((budget - shared) / per)));
+}
+
 emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_receiver *rec, int nrec,
                    unsigned chan_mask, const double *freq_hz, int nfreq, hipStream_t stream) {
     Acq &A = m->acq;
@@ -575,16 +616,12 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     A.sscale.assign(nsrc, 1.0);
     for (int s = 0; s < nsrc; ++s) {
         const emm_source &S = src[s];
-        if (S.comp < 0 || S.comp > 2 || !std::isfinite(S.moment) || S.moment == 0.0 ||
-            !std::isfinite(S.x) || !std::isfinite(S.y) || !std::isfinite(S.z))
-            return fail(m, EMM_ERR_ARG, "source component must be 0..2 with a finite non-zero moment");
+        emm_status cs = check_source(m, S);
+        if (cs != EMM_OK) return cs;
         const double p[3] = {S.x, S.y, S.z};
         double w[3][2 * emm::kMaxR];
         int base[3];
-        for (int a = 0; a < 3; ++a) {
-            base[a] = emm::point_stencil(coords(a, a == S.comp), p[a], r, w[a]);
-            if (!inside(a, base[a])) return fail(m, EMM_ERR_GEOMETRY, "source stencil leaves the interior");
-        }
+        for (int a = 0; a < 3; ++a) base[a] = emm::point_stencil(coords(a, a == S.comp), p[a], r, w[a]);
         // control volume: primal interval along comp, dual intervals across
         double ext[3][2 * emm::kMaxR];
         for (int a = 0; a < 3; ++a)
@@ -782,7 +819,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.ce1 = m->ce[0];
     P.ce2 = m->ce[1];
     P.ce3 = m->ce[2];
-    P.cei = choose_compact(m, fstride, nsrc) ? m->cei : nullptr;
+    P.cei = choose_compact(m, nsrc) ? m->cei : nullptr;
     P.cet = m->cet;
     P.ncet = m->ncet;
     P.ch = (float)(m->dt / kMu0);
@@ -884,16 +921,6 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
 
 emm_status autotune(emm_model *m, hipStream_t stream);
 
-// bytes of one source's full time-stepping state (fields + CPML memories)
-size_t state_floats(const emm_model *m) {
-    const long long plane = (long long)m->pitch * m->np[1];
-    const long long fstride = plane * m->np[2];
-    const int nb = m->nb;
-    const long long psxs = nb ? (long long)m->np[2] * m->np[1] * 2 * nb : 0;
-    const long long psys = nb ? (long long)m->np[2] * 2 * nb * m->pitch : 0;
-    const long long pszs = nb ? (long long)2 * nb * plane : 0;
-    return (size_t)(6 * fstride + 4 * (psxs + psys + pszs));
-}
 
 // Checkpoint c of buffer `base` <-> live state copies (fields and CPML
 // memories of all sources).
@@ -1611,12 +1638,39 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     if (!green) return fail(m, EMM_ERR_ARG, "NULL output pointer");
     emm_status st;
     hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
-    if ((st = prepare(m, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq, stream)) != EMM_OK) return st;
-    if ((st = autotune(m, stream)) != EMM_OK) return st;
     const bool leap = m->opt.fused && m->opt.checkpoint_every == 0 && !m->opt.airwave &&
                       !(m->opt.converge_tol > 0.0);
-    if ((st = leap ? leap_loop(m, stream) : time_loop(m, stream, m->opt.checkpoint_every)) != EMM_OK) return st;
-    return write_green(m, stream, green);
+    // sources in groups, one time loop per group; the checkpoints that a
+    // gradient reuses and a batch-wide convergence stop need every source in
+    // one loop.  Every source is checked before the first group runs.
+    const int g = (src && nsrc > 1 && m->opt.checkpoint_every == 0 && !(m->opt.converge_tol > 0.0))
+                      ? source_group(m, nsrc) : nsrc;
+    if (g < nsrc)
+        for (int s = 0; s < nsrc; ++s)
+            if ((st = check_source(m, src[s])) != EMM_OK) return st;
+    double fwd_ms = 0.0, e_ms = 0.0, h_ms = 0.0;
+    long long e_n = 0, h_n = 0;
+    for (int g0 = 0; g0 < nsrc || g0 == 0; g0 += std::max(g, 1)) {
+        const int ng = std::min(g, nsrc - g0);
+        if ((st = prepare(m, src ? src + g0 : src, ng, rec, nrec, chan_mask, freq_hz, nfreq, stream)) != EMM_OK)
+            return st;
+        if ((st = autotune(m, stream)) != EMM_OK) return st;
+        if ((st = leap ? leap_loop(m, stream) : time_loop(m, stream, m->opt.checkpoint_every)) != EMM_OK) return st;
+        const size_t per_src = (size_t)m->acq.nrec * m->acq.nch * m->acq.nf * 2;
+        if ((st = write_green(m, stream, green + (size_t)g0 * per_src)) != EMM_OK) return st;
+        fwd_ms += m->info.forward_ms;
+        e_ms += m->info.e_kernel_ms;
+        h_ms += m->info.h_kernel_ms;
+        e_n += m->info.e_launches;
+        h_n += m->info.h_launches;
+    }
+    m->info.forward_ms = fwd_ms;
+    m->info.e_kernel_ms = e_ms;
+    m->info.h_kernel_ms = h_ms;
+    m->info.e_launches = e_n;
+    m->info.h_launches = h_n;
+    m->info.src_group = g;
+    return EMM_OK;
 }
 
 emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, void *hip_stream) {
@@ -1645,7 +1699,33 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
             return st;
         if ((st = autotune(J.model, stream)) != EMM_OK) return st;
     }
-    if ((st = time_loop_jobs(ms, graph_steps > 0 ? graph_steps : 64, stream)) != EMM_OK) return st;
+    // jobs in consecutive groups, one graph per group, group after group
+    // (src_group of the first job's model: -1 all jobs in one graph, k > 0
+    // k jobs per graph, 0 as many as keep their arrays within the cache
+    // budget of source_group; a job that alone exceeds it runs by itself)
+    const int rule = ms[0]->opt.src_group;
+    const double budget = 160.0 * (1 << 20);
+    std::vector<emm_model *> group;
+    double held = 0.0;
+    for (int j = 0; j <= njobs; ++j) {
+        double need = 0.0;
+        if (j < njobs) {
+            emm_model *m = ms[j];
+            need = 4.0 * (double)state_floats(m) * jobs[j].nsrc +
+                   (double)m->pitch * m->np[1] * m->np[2] * (m->acq.Pe.cei ? 4.0 : 12.0);
+        }
+        const bool full = rule < 0 ? false : rule > 0 ? (int)group.size() == rule : held + need > budget;
+        if (!group.empty() && (j == njobs || full)) {
+            if ((st = time_loop_jobs(group, graph_steps > 0 ? graph_steps : 64, stream)) != EMM_OK) return st;
+            for (emm_model *m : group) m->info.src_group = (int)group.size();
+            group.clear();
+            held = 0.0;
+        }
+        if (j < njobs) {
+            group.push_back(ms[j]);
+            held += need;
+        }
+    }
     for (int j = 0; j < njobs; ++j)
         if ((st = write_green(jobs[j].model, stream, jobs[j].green)) != EMM_OK) return st;
     return EMM_OK;

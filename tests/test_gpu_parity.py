@@ -110,6 +110,25 @@ def test_batched_equals_single_sources(emm):
         assert np.array_equal(Gb[s:s + 1], Gs)
 
 
+def test_source_groups_equal_one_loop(emm):
+    """emm_forward running the sources in groups (2 + 2 + 1 time loops, one
+    after another) gives the one-loop batch bit for bit, and checks every
+    source before it runs the first group."""
+    w = configs.small_case(seed=14, nsrc=5, src_comp=(0, 1, 2, 0, 2), shape=(28, 26, 24), nt=160)
+    G1, i1 = _run(emm, w, src_group=-1)
+    G2, i2 = _run(emm, w, src_group=2, profile=1)
+    G3, i3 = _run(emm, w)                  # automatic: this small grid fits all five
+    assert (i1["src_group"], i2["src_group"], i3["src_group"]) == (5, 2, 5)
+    assert np.array_equal(G1, G2) and np.array_equal(G1, G3)
+    assert i2["e_launches"] > 0 and i2["forward_ms"] > 0
+    bad = w.sources.copy()
+    bad[4] = [1e6, 0.0, 0.0]
+    with emm.Model(w, src_group=2) as m:
+        with pytest.raises(emm.EmmError) as e:
+            m.forward(sources=bad)
+        assert e.value.status == -4
+
+
 def test_convergence_stop_matches_oracle(emm):
     """The lowest-frequency convergence stop: the GPU stops at the same
     check as the oracle (measure 1.6e-4 at step 1100, 2.4e-5 at 1200 for
@@ -195,16 +214,22 @@ def test_multi_model_batch_equals_single_forwards(emm):
           configs.small_case(seed=42, shape=(24, 22, 20), nt=100, rd=1)]
     singles = [_run(emm, w)[0] for w in ws]
     models = [emm.Model(w) for w in ws]
+    one = emm.Model(ws[0], src_group=1)      # as the first job: one job per graph
     try:
         print("[gpu] forward_models of 3 models", flush=True)
         outs = emm.forward_models(models, graph_steps=32)
         infos = [m.info() for m in models]
+        print("[gpu] forward_models of 3 models, one graph each", flush=True)
+        outs1 = emm.forward_models([one] + models[1:], graph_steps=32)
+        infos1 = [m.info() for m in [one] + models[1:]]
     finally:
-        for m in models:
+        for m in models + [one]:
             m.close()
-    for a, b in zip(outs, singles):
-        assert np.array_equal(a, b)
+    for a, b, c in zip(outs, singles, outs1):
+        assert np.array_equal(a, b) and np.array_equal(c, b)
     assert [i["nt"] for i in infos] == [150, 230, 100]
+    assert [i["src_group"] for i in infos] == [3, 3, 3]      # small grids share one graph
+    assert [i["src_group"] for i in infos1] == [1, 1, 1]
     G_o, _ = F.forward(ws[1])
     rep = compare(outs[1], G_o, ws[1].channels)
     print(f"[parity] multi-model job 1: {rep}", flush=True)
