@@ -124,6 +124,9 @@ typedef struct {
                               Infinity Cache between steps, or all when one source alone does
                               not fit; -1 = all; k > 0 = k. With checkpoint_every or converge_tol
                               set, all sources run in one loop [0] */
+    int    tile_x;         /* columns per block of the stencil kernels: 64 (x 4 rows) or 32 (x 8
+                              rows); 0 = autotuned with tile_kz = -1, else 32 where it leaves
+                              fewer idle lanes in the last x tile of a row or at rd >= 3 [0] */
 } emm_options;
 
 /* A point electric dipole (the acquisition of Section 5): position in
@@ -159,6 +162,7 @@ typedef struct {
     int    ce_table;         /* 1: the last forward's E step read dt/eps in the compact form */
     int    src_group;        /* sources per time loop of the last emm_forward (jobs per graph
                                 after emm_forward_batch) */
+    int    tile_x;           /* columns per block of the last forward's stencil kernels */
 } emm_info;
 
 /* Fill *o with the defaults above. */

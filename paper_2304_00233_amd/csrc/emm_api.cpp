@@ -65,6 +65,7 @@ struct Tune {
     int kz = 0;        // z planes per block
     int stream = 0;    // nontemporal hints
     int compact = 0;   // compact dt/eps in the E step
+    int tx = 64;       // tile width of the step kernels
 };
 
 struct emm_model {
@@ -214,9 +215,33 @@ int choose_compact(const emm_model *m, int nsrc) {
     return 1;
 }
 
+// Tile width of the step kernels (64 x 4 or 32 x 8 columns): the option,
+// the autotuner's choice, else 32 where it leaves clearly fewer idle lanes
+// in the last x tile of a row, or at r >= 3 (less y halo per cell).
+int choose_tx(const emm_model *m, int nsrc) {
+    if (m->opt.tile_x > 0) return m->opt.tile_x;
+    if (m->opt.tile_kz < 0) {
+        auto it = m->tuned.find(nsrc);
+        if (it != m->tuned.end()) return it->second.tx;
+    }
+    const int valid = m->np[0] - 2 * m->r;
+    auto lanes = [&](int w) { return (m->np[0] - m->r + w - 1) / w * w; };
+    const double e64 = (double)valid / lanes(64), e32 = (double)valid / lanes(32);
+    return (m->r >= 3 || e32 > e64 + 0.02) ? 32 : 64;
+}
+
+// x and y tiles over the update set i, j in [r, n - 1 - r] (x tiles start at 0)
+void set_tiles(emm::StepParams &P, const emm_model *m, int tx) {
+    const int rows = emm::kStepThreads / tx;
+    P.tx = tx;
+    P.xt = (m->np[0] - m->r + tx - 1) / tx;
+    P.yt = (m->np[1] - 2 * m->r + rows - 1) / rows;
+}
+
 // launch choices of the last run, and the E step's bytes that follow from them
 void note_run(emm_model *m, const emm::StepParams &Pe) {
     m->info.tile_kz = Pe.kz;
+    m->info.tile_x = Pe.tx;
     m->info.nontemporal = Pe.stream;
     m->info.ce_table = Pe.cei != nullptr;
     step_bytes(m, m->info.e_bytes, m->info.h_bytes, Pe.cei != nullptr);
@@ -253,6 +278,7 @@ emm_status emm_default_options(emm_options *o) {
     o->converge_every = 100;
     o->ce_table = -1;
     o->src_group = 0;
+    o->tile_x = 0;
     return EMM_OK;
 }
 
@@ -314,7 +340,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
         opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
         opt.airwave < 0 || opt.airwave > 1 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
-        opt.fused < 0 || opt.fused > 1 || opt.ce_table < -1 || opt.ce_table > 1 || opt.src_group < -1 ||
+        opt.fused < 0 || opt.fused > 1 || opt.ce_table < -1 || opt.ce_table > 1 || opt.src_group < -1 || (opt.tile_x != 0 && opt.tile_x != 32 && opt.tile_x != 64) ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -797,8 +823,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.plane = plane;
     P.fstride = fstride;
     P.nb = nb;
-    P.xt = m->pitch / emm::kTileX;
-    P.yt = (m->np[1] - 2 * r + emm::kTileY - 1) / emm::kTileY;
+    set_tiles(P, m, choose_tx(m, nsrc));
     P.kz = choose_kz(m, P.xt, P.yt, nsrc);
     P.zc = (z_planes(m) + P.kz - 1) / P.kz;
     P.kmin = kmin_of(m);
@@ -1554,8 +1579,9 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
         if (kz <= 64 && (cand.empty() || cand.back() != kz)) cand.push_back(kz);
     }
     if (std::find(cand.begin(), cand.end(), A.Pe.kz) == cand.end()) cand.push_back(A.Pe.kz);
-    std::vector<int> hints = {0, 1}, compacts = {0};
+    std::vector<int> hints = {0, 1}, compacts = {0}, widths = {64, 32};
     if (m->opt.nontemporal >= 0) hints = {m->opt.nontemporal};
+    if (m->opt.tile_x > 0) widths = {m->opt.tile_x};
     if (m->cei && m->opt.ce_table == -1) compacts = {0, 1};
     else if (m->cei && m->opt.ce_table == 1) compacts = {1};
     hipEvent_t e0, e1;
@@ -1563,6 +1589,8 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     HIP_OK(m, hipEventCreate(&e1));
     auto time_it = [&](const Tune &c, int steps, float &ms) -> emm_status {
         emm::StepParams Pe = A.Pe, Ph = A.Ph;
+        set_tiles(Pe, m, c.tx);
+        set_tiles(Ph, m, c.tx);
         Pe.kz = Ph.kz = c.kz;
         Pe.zc = Ph.zc = (nzv + c.kz - 1) / c.kz;
         Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
@@ -1585,24 +1613,27 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     std::vector<std::pair<float, int>> first;   // (ms, index into tried)
     std::vector<Tune> tried;
     emm_status st;
-    for (int cp : compacts)
-        for (int sh : hints)
-            for (int kz : cand) {
-                Tune c;
-                c.kz = kz;
-                c.stream = sh;
-                c.compact = cp;
-                float ms = 0.f;
-                if ((st = time_it(c, 6, ms)) != EMM_OK) return st;
-                first.push_back({ms, (int)tried.size()});
-                tried.push_back(c);
-            }
+    for (int tx : widths)
+        for (int cp : compacts)
+            for (int sh : hints)
+                for (int kz : cand) {
+                    Tune c;
+                    c.kz = kz;
+                    c.stream = sh;
+                    c.compact = cp;
+                    c.tx = tx;
+                    float ms = 0.f;
+                    if ((st = time_it(c, 6, ms)) != EMM_OK) return st;
+                    first.push_back({ms, (int)tried.size()});
+                    tried.push_back(c);
+                }
     std::sort(first.begin(), first.end());
     float best = 1e30f;
     Tune pick;
     pick.kz = A.Pe.kz;
     pick.stream = A.Pe.stream;
     pick.compact = A.Pe.cei != nullptr;
+    pick.tx = A.Pe.tx;
     if (!first.empty()) pick = tried[first[0].second];
     for (size_t c = 0; c < std::min<size_t>(4, first.size()); ++c) {
         float ms = 0.f;
@@ -1617,6 +1648,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     HIP_OK(m, hipGetLastError());
     m->tuned[A.nsrc] = pick;
     for (emm::StepParams *P : {&A.Pe, &A.Ph}) {
+        set_tiles(*P, m, pick.tx);
         P->kz = pick.kz;
         P->zc = (nzv + pick.kz - 1) / pick.kz;
         P->nstencil = P->xt * P->yt * P->zc * A.nsrc;
@@ -1997,9 +2029,9 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     PE.r = r;
     PE.nb = nb;
     PE.nsrc = nsrc;
-    PE.kz = A.Pe.kz;                          // tiles and z chunks of the forward kernels
-    PE.xt = A.Pe.xt;
-    PE.yt = A.Pe.yt;
+    PE.kz = A.Pe.kz;                          // z chunks of the forward kernels, 64 x 4 tiles
+    PE.xt = m->pitch / emm::kTileX;
+    PE.yt = (n2 - 2 * r + emm::kTileY - 1) / emm::kTileY;
     PE.zc = A.Pe.zc;
     PE.nstencil = PE.xt * PE.yt * PE.zc * nsrc;
     PE.fstride = fstride;

@@ -11,6 +11,11 @@ namespace emm {
 constexpr int kTileX = 64;     // one wavefront row along x (wave64)
 constexpr int kMaxR = 4;       // 8th order in space at most
 constexpr int kTileY = 4;      // rows (wavefronts) per thread block
+// The forward step kernels run 256-thread tiles of 64 x 4 or 32 x 8
+// columns (StepParams::tx): 32-wide tiles leave fewer idle lanes in the
+// last tile of a row and stage less y halo per cell; 64-wide ones keep the
+// row index wave-uniform.
+constexpr int kStepThreads = kTileX * kTileY;
 constexpr int kCeTable = 256;  // distinct dt/eps values of a model in the compact form
 
 // Everything one half-step kernel needs; passed by value.
@@ -21,6 +26,7 @@ struct StepParams {
     long long fstride;          // one source's field array: plane * n3
     int nb;
     // launch decomposition
+    int tx;                     // tile width: 64 (x 4 rows) or 32 (x 8 rows)
     int xt, yt, zc, kz;         // x tiles, y tiles, z chunks, planes per chunk
     int kmin;                   // first updated z plane (r, or the surface node under air)
     int nsrc;

@@ -110,19 +110,21 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
 //
 // CI (E step only): dt/eps comes from the compact form, one index word per
 // cell (4 bytes instead of 12) into a table of the model's distinct values,
-// held in LDS.
-template <int R, bool HS, bool ST, bool CI>
+// held in LDS.  TX: tile width (TX x NT/TX columns per block).
+template <int R, bool HS, bool ST, bool CI, int TX>
 __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg) {
     const int n = (p.step_base ? *p.step_base : 0) + n_arg;
     constexpr int L = 2 * R;
+    constexpr int TYS = NT / TX;
+    static_assert(TX * TYS == NT && (TX & (TX - 1)) == 0, "tile of NT threads, power-of-two width");
     constexpr int HL = HS ? R - 1 : R;        // halo below the own index
-    constexpr int W = kTileX + L - 1;         // LDS row length incl. halo
-    constexpr int HR = TY + L - 1;            // LDS rows incl. halo
+    constexpr int W = TX + L - 1;             // LDS row length incl. halo
+    constexpr int HR = TYS + L - 1;           // LDS rows incl. halo
     constexpr int N3 = (HR * W + NT - 1) / NT;              // A3 staging loads per thread
-    constexpr int N1 = ((L - 1) * kTileX + NT - 1) / NT;    // A1 halo loads per thread
+    constexpr int N1 = ((L - 1) * TX + NT - 1) / NT;        // A1 halo loads per thread
     __shared__ float sA3[2][HR][W];           // x and y taps
-    __shared__ float sA2[2][TY][W];           // x taps
-    __shared__ float sA1[2][HR][kTileX];      // y taps
+    __shared__ float sA2[2][TYS][W];          // x taps
+    __shared__ float sA1[2][HR][TX];          // y taps
     __shared__ float sCe[CI ? kCeTable : 1];
     static_assert(kCeTable <= NT, "one table entry per thread");
 
@@ -146,14 +148,14 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     const int byt = t % p.yt;
     const int bzt = t / p.yt;
 
-    // The row index is wave-uniform (one row per wavefront); declaring it so
-    // moves the y coefficients and y-slab values to scalar registers.  That
-    // frees vector registers but adds scalar spills; measured, it pays in
-    // the E step and in the H step at 8th order only.
-    constexpr bool kScalarRow = !HS || R >= 4;
-    const int tid = threadIdx.x, tx = tid & 63;
-    const int ty = kScalarRow ? __builtin_amdgcn_readfirstlane(tid >> 6) : tid >> 6;
-    const int i0 = bxt * kTileX, j0 = R + byt * TY;
+    // With 64-wide tiles the row index is wave-uniform (one row per
+    // wavefront); declaring it so moves the y coefficients and y-slab values
+    // to scalar registers, which pays in the E step and in the H step at
+    // 8th order.
+    constexpr bool kScalarRow = TX == 64 && (!HS || R >= 4);
+    const int tid = threadIdx.x, tx = tid & (TX - 1);
+    const int ty = kScalarRow ? __builtin_amdgcn_readfirstlane(tid / TX) : tid / TX;
+    const int i0 = bxt * TX, j0 = R + byt * TYS;
     const int i = i0 + tx, j = j0 + ty;
     const int k0 = p.kmin + bzt * p.kz;
     const int k1 = min(k0 + p.kz, p.n3 - R);
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     // row e / W, column e % W of the LDS tile, i.e. global (j0 - HL + row,
     // i0 - HL + col); out-of-array elements stage zeros.
     // (LDS index of A3 element u: tid + u * NT; of A1 halo element u: row
-    // ly1(u) * 64 + tx.)
+    // ly1(u) * TX + tx.)
     int o3[N3];        // plane offset, or -1 (outside the array or the tile)
 #pragma unroll
     for (int u = 0; u < N3; ++u) {
@@ -234,20 +236,20 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         o3[u] = (e < HR * W && gj >= 0 && gj < p.n2 && gi >= 0 && gi < p.pitch) ? gj * p.pitch + gi : -1;
     }
     auto ly1 = [&](int u) {
-        const int hy = (tid + u * NT) >> 6;
-        return hy < HL ? hy : TY + hy;
+        const int hy = (tid + u * NT) / TX;
+        return hy < HL ? hy : TYS + hy;
     };
     int o1[N1];
 #pragma unroll
     for (int u = 0; u < N1; ++u) {
         const int e = tid + u * NT;
         const int gj = j0 - HL + ly1(u);
-        o1[u] = (e < (L - 1) * kTileX && gj >= 0 && gj < p.n2) ? gj * p.pitch + i0 + tx : -1;
+        o1[u] = (e < (L - 1) * TX && gj >= 0 && gj < p.n2) ? gj * p.pitch + i0 + tx : -1;
     }
     int o2 = -1, l2 = -1;
-    if (tid < TY * (L - 1)) {
+    if (tid < TYS * (L - 1)) {
         const int hy = tid / (L - 1), hx = tid % (L - 1);
-        const int lx = hx < HL ? hx : kTileX + hx;
+        const int lx = hx < HL ? hx : TX + hx;
         const int gi = i0 - HL + lx, gj = min(j0 + hy, p.n2 - 1);
         l2 = hy * W + lx;
         o2 = (gi >= 0 && gi < p.pitch) ? gj * p.pitch + gi : -1;
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         float *s1 = &sA1[b][0][0];
 #pragma unroll
         for (int u = 0; u < N1; ++u)
-            if (u < N1 - 1 || tid + u * NT < (L - 1) * kTileX) s1[ly1(u) * kTileX + tx] = f1[u];
+            if (u < N1 - 1 || tid + u * NT < (L - 1) * TX) s1[ly1(u) * TX + tx] = f1[u];
         if (l2 >= 0) (&sA2[b][0][0])[l2] = o2 >= 0 ? f2 : 0.f;
         sA2[b][ty][tx + HL] = q2[HL];
         sA1[b][ty + HL][tx] = q1[HL];
@@ -740,8 +742,13 @@ void launch_leap(int r, const StepParams &pe, const StepParams &ph, const LeapPa
 template <int R, bool HS, bool ST, bool CI>
 static void launch_r(const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const dim3 grid(p.nrecblk + p.nstencil), block(NT);
-    if (t0 || t1) hipExtLaunchKernelGGL((step_kernel<R, HS, ST, CI>), grid, block, 0, s, t0, t1, 0, p, n);
-    else hipLaunchKernelGGL((step_kernel<R, HS, ST, CI>), grid, block, 0, s, p, n);
+    if (p.tx == 32) {
+        if (t0 || t1) hipExtLaunchKernelGGL((step_kernel<R, HS, ST, CI, 32>), grid, block, 0, s, t0, t1, 0, p, n);
+        else hipLaunchKernelGGL((step_kernel<R, HS, ST, CI, 32>), grid, block, 0, s, p, n);
+    } else {
+        if (t0 || t1) hipExtLaunchKernelGGL((step_kernel<R, HS, ST, CI, 64>), grid, block, 0, s, t0, t1, 0, p, n);
+        else hipLaunchKernelGGL((step_kernel<R, HS, ST, CI, 64>), grid, block, 0, s, p, n);
+    }
 }
 
 template <bool HS, bool ST, bool CI>

@@ -92,14 +92,19 @@ def test_kahan_fp32_accumulators(emm):
     _, _, rep = _check(emm, w, "kahan", dft_mode=1)
 
 
-def test_bitwise_determinism_runs_and_tiles(emm):
-    w = configs.small_case(seed=9, shape=(40, 30, 37), nt=200)
+@pytest.mark.parametrize("rd", [2, 4])
+def test_bitwise_determinism_runs_and_tiles(emm, rd):
+    """Runs, z chunks and both tile widths (64 x 4 and 32 x 8 columns) give
+    the same results bit for bit."""
+    w = configs.small_case(seed=9, shape=(40, 30, 37), nt=200, rd=rd)
     G1, _ = _run(emm, w)
     G2, _ = _run(emm, w)
     G3, i3 = _run(emm, w, tile_kz=3)
-    assert i3["tile_kz"] == 3
-    assert np.array_equal(G1, G2)
-    assert np.array_equal(G1, G3)
+    G4, i4 = _run(emm, w, tile_x=32, tile_kz=7)
+    G5, i5 = _run(emm, w, tile_x=64)
+    assert i3["tile_kz"] == 3 and (i4["tile_x"], i5["tile_x"]) == (32, 64)
+    for G in (G2, G3, G4, G5):
+        assert np.array_equal(G1, G)
 
 
 def test_batched_equals_single_sources(emm):
