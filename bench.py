@@ -26,9 +26,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # HBM traffic of one E-step launch on the marine workload, measured with
 # rocprofv3 --pmc FETCH_SIZE (x 2.0) and --pmc WRITE_SIZE (x 1.0), the factors
-# from a 1 GiB copy kernel: 69 207.9 KiB read and 46 142.1 KiB written.  Valid for
-# the kernel as profiled; set to None when the kernel changes until re-measured.
-E_STEP_TRAFFIC_BYTES = (69207.9 * 2.0 + 46142.1 * 1.0) * 1024
+# from a 1 GiB copy kernel: 54 421.1 KiB read and 46 143.4 KiB written (32 x 8
+# tiles, 5 planes per block, compact dt/eps).  Valid for the kernel as
+# profiled; None when the kernel has changed since, until re-measured.
+E_STEP_TRAFFIC_BYTES = (54421.1 * 2.0 + 46143.4 * 1.0) * 1024
 # the same for one launch of the fused step kernel (None until measured)
 LEAP_TRAFFIC_BYTES = None
 
@@ -194,6 +195,8 @@ def main():
     ap.add_argument("--fused", type=int, default=0, choices=[0, 1],
                     help="1: one fused launch per time step (E and H updates)")
     ap.add_argument("--tile-kz", type=int, default=-1, help="z planes per block (-1: autotuned)")
+    ap.add_argument("--tile-x", type=int, default=0, choices=(0, 32, 64),
+                    help="columns per block of the stencil kernels (0: autotuned or by the grid)")
     ap.add_argument("--batched", type=int, default=16,
                     help="sources of the batched comparison (0: skip)")
     ap.add_argument("--grad-group", type=int, default=8)
@@ -267,7 +270,8 @@ def main():
         w = w.with_(nt=args.nt)
     log(f"[bench] workload {w.name} padded cells {w.padded_cells}")
 
-    model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz, fused=args.fused)
+    model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz, fused=args.fused,
+                      tile_x=args.tile_x)
     for i in range(args.warmup):
         model.forward()
         log(f"[bench] warmup {i} done")
@@ -297,7 +301,8 @@ def main():
     achieved = kbytes / e_avg_s / 1e9
     log(f"[bench] nt={nt} wall/forward={ms_per_step:.1f} ms device loop/forward="
         f"{dev_ms / args.steps:.1f} ms e_step avg={e_avg_s * 1e6:.2f} us "
-        f"h_step avg={h_avg_s * 1e6:.2f} us tile_kz={info['tile_kz']}")
+        f"h_step avg={h_avg_s * 1e6:.2f} us tile_kz={info['tile_kz']} tile_x={info['tile_x']} "
+        f"nontemporal={info['nontemporal']} ce_table={info['ce_table']}")
     out = {
         "metric": "FDTD cell-updates/s (Gcell*step/s) + % HBM peak",
         "value": value, "unit": "Gcell*step/s", "n_gpus": 1, "steps": args.steps,
@@ -318,6 +323,9 @@ def main():
                      if args.workload == "marine" else None,
                      "bytes_per_launch": kbytes, "avg_launch_us": e_avg_s * 1e6},
         "device_loop_ms_per_step": dev_ms / args.steps,
+        "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"],
+                   "nontemporal": info["nontemporal"], "compact_dt_eps": info["ce_table"],
+                   "graph_steps": args.graph},
         "fused_step": fused,
     }
     if not fused:
