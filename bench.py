@@ -167,10 +167,10 @@ def large_fwd_grad(emm, nt: int, group: int, graph: int):
             sl = slice(g0, min(8, g0 + group))
             m.gradient(g_obs=G_obs[sl], sources=w.sources[sl], src_comp=w.src_comp[sl])
             i = m.info()
-            sched.append([i["ckpt_outer"], i["ckpt_inner"], i["ckpt_bytes"] / 2 ** 30])
+            sched.append([i["ckpt_outer"], i["ckpt_inner"], i["ckpt_bytes"] / 2 ** 30, i["src_group"]])
             log(f"[bench] large: gradient of sources {g0}..{sl.stop - 1} done, schedule {sched[-1]}")
         out["forward_gradient_s"] = time.perf_counter() - t
-        out["checkpoint_schedule_outer_inner_GiB"] = sched
+        out["checkpoint_schedule_outer_inner_GiB_sources_per_sweep"] = sched
         out["cells"] = m.info()["cells"]
     out["batched_forward_vs_plain_loop"] = out["plain_forward_loop_s"] / out["batched_forward_s"]
     out["forward_gradient_over_plain_forward_loop"] = out["forward_gradient_s"] / out["plain_forward_loop_s"]
@@ -206,8 +206,9 @@ def main():
     ap.add_argument("--large-fwd-grad", type=int, default=0, metavar="NT",
                     help="also time the 8-source 8th-order forward + gradient on the 400x400x200 "
                          "grid with NT time steps (0: skip)")
-    ap.add_argument("--large-group", type=int, default=2,
-                    help="sources per emm_gradient call of --large-fwd-grad")
+    ap.add_argument("--large-group", type=int, default=8,
+                    help="sources per emm_gradient call of --large-fwd-grad (the library then "
+                         "groups them per sweep by its checkpoint plan)")
     ap.add_argument("--gradient-sample", type=int, default=0, metavar="NT",
                     help="only run one forward + gradient of the marine (or, with --workload "
                          "large, the large-grid) workload cut to NT steps (for kernel traces of "

@@ -123,7 +123,8 @@ typedef struct {
                               arrays of one step within 160 MiB, so they stay in the 256 MB
                               Infinity Cache between steps, or all when one source alone does
                               not fit; -1 = all; k > 0 = k. With checkpoint_every or converge_tol
-                              set, all sources run in one loop [0] */
+                              set, all sources run in one loop. emm_gradient groups its sources
+                              too (0 = the most whose checkpoints fit one level, see there) [0] */
     int    tile_x;         /* columns per block of the stencil kernels: 64 (x 4 rows) or 32 (x 8
                               rows); 0 = autotuned with tile_kz = -1, else 32 where it leaves
                               fewer idle lanes in the last x tile of a row or at rd >= 3 [0] */
@@ -243,7 +244,13 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
  * the one-level interval of least memory if it fits in the free device
  * memory (after the adjoint's own arrays), else the two-level pair of least
  * memory; EMM_ERR_OOM if neither fits (run fewer sources per call).  The
- * result does not depend on the schedule (bitwise).  The scalar L is either
+ * sources run in groups, one forward + reverse sweep per group, by the
+ * src_group option: 0 = the most sources whose planned checkpoints fit one
+ * level (a second level costs one more forward pass, batching saves only a
+ * few per cent), else the most that fit two levels; -1 = all; k > 0 = k;
+ * all of them when checkpoint_every is set or the last forward's
+ * checkpoints are reused (info.src_group: the group size).  The result
+ * does not depend on the schedule or the grouping (bitwise).  The scalar L is either
  *   g_obs != NULL: L = 1/2 sum over all results of |log(G/G_obs)|^2 (real
  *                  part: log-amplitude residual, imaginary part: phase
  *                  residual), returned in *misfit (may be NULL), or

@@ -574,6 +574,23 @@ bool same_acquisition(const Acq &a, const emm_source *src, int nsrc, const emm_r
 // Validate the acquisition, build the host tables (stencils, wavelet, DTFT
 // phases, CPML), upload them and fill the kernel parameters (Sections 3.1,
 // 3.4, 3.5; see emm_forward in emm.h).
+// Time steps of a forward: the option, else (Section 3.5) the wavelet's
+// duration plus the time for the lowest frequency's damped mode to decay by
+// 1e6, rounded up to a multiple of 100.  Frequencies must be valid.
+int steps_for(const emm_model *m, const double *freq_hz, int nfreq) {
+    if (m->opt.nt > 0) return m->opt.nt;
+    double fmax = 0.0, fmin = 1e300;
+    for (int f = 0; f < nfreq; ++f) {
+        fmax = std::max(fmax, freq_hz[f]);
+        fmin = std::min(fmin, freq_hz[f]);
+    }
+    const double fp = m->opt.wavelet_fpeak > 0.0 ? m->opt.wavelet_fpeak : 2.0 * std::sqrt(fmax * m->opt.f0);
+    const double tau = 1.0 / (kPi * fp);
+    const double decay = emm::omega_prime(fmin, m->omega0).imag();
+    const double T = 7.0 * tau + std::log(1e6) / decay;
+    return (int)(std::ceil(T / m->dt / 100.0) * 100.0);
+}
+
 // A source's component, moment and position: its (2r)^3 stencil on the grid
 // of its E component must lie inside the interior.
 emm_status check_source(emm_model *m, const emm_source &S) {
@@ -732,13 +749,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
         fmin = std::min(fmin, freq_hz[f]);
     }
     const double fp = m->opt.wavelet_fpeak > 0.0 ? m->opt.wavelet_fpeak : 2.0 * std::sqrt(fmax * m->opt.f0);
-    int nt = m->opt.nt;
-    if (nt == 0) {
-        const double tau = 1.0 / (kPi * fp);
-        const double decay = emm::omega_prime(fmin, m->omega0).imag();
-        const double T = 7.0 * tau + std::log(1e6) / decay;
-        nt = (int)(std::ceil(T / m->dt / 100.0) * 100.0);
-    }
+    const int nt = steps_for(m, freq_hz, nfreq);
     const std::vector<double> sw = emm::wavelet(nt, m->dt, fp);
     std::vector<float> swf(sw.begin(), sw.end());
     A.wavelet = swf;
@@ -1763,46 +1774,54 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
     return EMM_OK;
 }
 
-emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm_receiver *rec,
-                        int nrec, unsigned chan_mask, const double *freq_hz, int nfreq,
-                        const double *g_obs, const double *g_bar, double *green, double *misfit,
-                        double *grad, void *hip_stream) {
-    if (!m) return fail(nullptr, EMM_ERR_ARG, "NULL model");
-    m->err.clear();
-    if (!grad || (g_obs == nullptr) == (g_bar == nullptr))
-        return fail(m, EMM_ERR_ARG, "need grad and exactly one of g_obs, g_bar");
-    if (m->opt.airwave) return fail(m, EMM_ERR_ARG, "the adjoint of the air boundary is not built");
-    if (m->opt.converge_tol > 0.0) return fail(m, EMM_ERR_ARG, "the gradient needs a fixed step count (converge_tol = 0)");
+// Device memory left for the checkpoints of a sweep over g sources: the
+// free memory plus what the checkpoint buffers already hold, minus what the
+// time-stepping state and the adjoint arrays of g sources still need and a
+// margin.
+emm_status ckpt_budget(emm_model *m, int g, size_t &bud) {
+    const long long fs = (long long)m->pitch * m->np[1] * m->np[2];
+    const size_t slab_src = (state_floats(m) - 6 * fs) / 2;     // 6 slab arrays per source
+    const size_t need[7] = {(size_t)6 * g * fs * sizeof(float),
+                            std::max<size_t>(1, 2 * g * slab_src) * sizeof(float),
+                            std::max<size_t>(1, g * slab_src) * sizeof(float),
+                            (size_t)3 * g * fs * sizeof(double),
+                            (size_t)3 * g * fs * sizeof(float),
+                            (size_t)6 * g * fs * sizeof(float),
+                            std::max<size_t>(1, 2 * g * slab_src) * sizeof(float)};
+    const DevBuf *have[7] = {&m->adjf, &m->adjq, &m->adjt, &m->grad, &m->grad32, &m->fields, &m->psi};
+    size_t fr = 0, tot = 0;
+    HIP_OK(m, hipMemGetInfo(&fr, &tot));
+    long long budget = (long long)fr + (long long)(m->ckpts.bytes + m->ickpts.bytes + m->snaps.bytes);
+    for (int b = 0; b < 7; ++b) budget -= (long long)(need[b] > have[b]->bytes ? need[b] - have[b]->bytes : 0);
+    budget -= (long long)(tot / 50) + (256LL << 20);
+    bud = budget > 0 ? (size_t)budget : 0;
+    return EMM_OK;
+}
+
+// One forward + reverse sweep over the sources given (see emm_gradient).
+// accumulate: add dL/dlog sigma onto grad and the misfit onto chi in the
+// order a single call over all sources would (so groups of sources give
+// the same bits); else start both from zero.
+emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm_receiver *rec, int nrec,
+                        unsigned chan_mask, const double *freq_hz, int nfreq, const double *g_obs,
+                        const double *g_bar, double *green, double &chi_acc, double *grad, bool accumulate,
+                        hipStream_t stream) {
     emm_status st;
-    hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
     // forward with checkpoints, unless the last forward stored them for the same acquisition
     const bool reuse = m->acq.ckpt > 0 && same_acquisition(m->acq, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq);
     if (!reuse) {
         if ((st = prepare(m, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq, stream)) != EMM_OK) return st;
         if ((st = autotune(m, stream)) != EMM_OK) return st;
     }
-    // checkpoint schedule: the budget is the free device memory plus what the
-    // checkpoint buffers already hold, minus what the adjoint arrays below
-    // still need and a margin
+    // checkpoint schedule within the memory left for it
     int c1 = 0, c2 = 0;
     {
         const Acq &A0 = m->acq;
         const long long fs = A0.Pe.fstride;
         const size_t S = state_floats(m) * A0.nsrc * sizeof(float);
         const size_t F = (size_t)3 * A0.nsrc * fs * sizeof(float);
-        const size_t slab_src = (state_floats(m) - 6 * fs) / 2;     // 6 slab arrays per source
-        const size_t need[5] = {(size_t)6 * A0.nsrc * fs * sizeof(float),
-                                std::max<size_t>(1, 2 * A0.nsrc * slab_src) * sizeof(float),
-                                std::max<size_t>(1, A0.nsrc * slab_src) * sizeof(float),
-                                (size_t)3 * A0.nsrc * fs * sizeof(double),
-                                (size_t)3 * A0.nsrc * fs * sizeof(float)};
-        const DevBuf *have[5] = {&m->adjf, &m->adjq, &m->adjt, &m->grad, &m->grad32};
-        size_t fr = 0, tot = 0;
-        HIP_OK(m, hipMemGetInfo(&fr, &tot));
-        long long budget = (long long)fr + (long long)(m->ckpts.bytes + m->ickpts.bytes + m->snaps.bytes);
-        for (int b = 0; b < 5; ++b) budget -= (long long)(need[b] > have[b]->bytes ? need[b] - have[b]->bytes : 0);
-        budget -= (long long)(tot / 50) + (256LL << 20);
-        const size_t bud = budget > 0 ? (size_t)budget : 0;
+        size_t bud = 0;
+        if ((st = ckpt_budget(m, A0.nsrc, bud)) != EMM_OK) return st;
         if (!plan_checkpoints(A0.nt, m->opt.graph_steps, reuse ? A0.ckpt : m->opt.checkpoint_every,
                               m->opt.checkpoint_inner, S, F, bud, c1, c2))
             return fail(m, EMM_ERR_OOM, "no checkpoint schedule fits in " + std::to_string(bud) +
@@ -1822,7 +1841,7 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     // Acoef = conj(gbar) dG/dacc, gbar = dL/dRe G + i dL/dIm G; for the log misfit
     // L = 1/2 sum |log(G/G_obs)|^2, gbar = r / conj(G), r = log(G/G_obs).
     std::vector<double2> Acoef(nd);
-    double chi = 0.0;
+    double chi = accumulate ? chi_acc : 0.0;
     bool nonfinite = false;
     for (size_t k = 0; k < nd; ++k) {
         const std::complex<double> c = green_factor(m, k);
@@ -1845,7 +1864,7 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
         Acoef[k] = make_double2(a.real(), a.imag());
     }
     if (nonfinite) return fail(m, EMM_ERR_NONFINITE, "a DTFT accumulator is not finite (unstable run?)");
-    if (misfit) *misfit = g_obs ? chi : 0.0;
+    chi_acc = g_obs ? chi : 0.0;
 
     // ---- adjoint set-up ----
     const int r = m->r, L = 2 * r, nb = m->nb, nt = A.nt;
@@ -2144,7 +2163,7 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
     HIP_OK(m, hipMemcpyAsync(g.data(), m->grad.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
     HIP_OK(m, hipStreamSynchronize(stream));
     const int nd0 = m->n[0], nd1 = m->n[1], nd2 = m->n[2];
-    std::fill(grad, grad + (size_t)3 * nd0 * nd1 * nd2, 0.0);
+    if (!accumulate) std::fill(grad, grad + (size_t)3 * nd0 * nd1 * nd2, 0.0);
     for (int c = 0; c < 3; ++c)
         for (int s = 0; s < nsrc; ++s)
             for (int k = r; k <= n3 - 1 - r; ++k) {
@@ -2159,6 +2178,63 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm
                     }
                 }
             }
+    return EMM_OK;
+}
+
+// Sources per forward + reverse sweep of emm_gradient: the src_group option,
+// else (0) the most sources whose checkpoints fit one level (a second level
+// costs one more forward pass, batching saves a few per cent), else the most
+// that fit two levels; all of them with a fixed checkpoint interval.
+int gradient_group(emm_model *m, int nsrc, int nt) {
+    if (m->opt.src_group > 0) return std::min(m->opt.src_group, nsrc);
+    if (m->opt.src_group < 0 || m->opt.checkpoint_every > 0) return nsrc;
+    const long long fs = (long long)m->pitch * m->np[1] * m->np[2];
+    int two = 0;
+    for (int g = nsrc; g >= 1; --g) {
+        size_t bud = 0;
+        if (ckpt_budget(m, g, bud) != EMM_OK) return nsrc;
+        int c1 = 0, c2 = 0;
+        const size_t S = state_floats(m) * g * sizeof(float), F = (size_t)3 * g * fs * sizeof(float);
+        if (!plan_checkpoints(nt, m->opt.graph_steps, 0, m->opt.checkpoint_inner, S, F, bud, c1, c2)) continue;
+        if (c2 >= c1) return g;
+        if (!two) two = g;
+    }
+    return two ? two : 1;
+}
+
+emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc, const emm_receiver *rec,
+                        int nrec, unsigned chan_mask, const double *freq_hz, int nfreq,
+                        const double *g_obs, const double *g_bar, double *green, double *misfit,
+                        double *grad, void *hip_stream) {
+    if (!m) return fail(nullptr, EMM_ERR_ARG, "NULL model");
+    m->err.clear();
+    if (!grad || (g_obs == nullptr) == (g_bar == nullptr))
+        return fail(m, EMM_ERR_ARG, "need grad and exactly one of g_obs, g_bar");
+    if (m->opt.airwave) return fail(m, EMM_ERR_ARG, "the adjoint of the air boundary is not built");
+    if (m->opt.converge_tol > 0.0) return fail(m, EMM_ERR_ARG, "the gradient needs a fixed step count (converge_tol = 0)");
+    hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
+    emm_status st;
+    double chi = 0.0;
+    // the checkpoints of the last forward serve only the same acquisition in one sweep
+    const bool reuse = m->acq.ckpt > 0 && same_acquisition(m->acq, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq);
+    bool freqs_ok = freq_hz && nfreq > 0;
+    for (int f = 0; freqs_ok && f < nfreq; ++f) freqs_ok = freq_hz[f] > 0.0 && std::isfinite(freq_hz[f]);
+    const int g = (!reuse && src && nsrc > 1 && freqs_ok) ? gradient_group(m, nsrc, steps_for(m, freq_hz, nfreq))
+                                                          : nsrc;
+    if (g < nsrc)
+        for (int s = 0; s < nsrc; ++s)
+            if ((st = check_source(m, src[s])) != EMM_OK) return st;
+    const size_t per_src = (size_t)nrec * __builtin_popcount(chan_mask & 0x3Fu) * (nfreq > 0 ? nfreq : 0) * 2;
+    for (int g0 = 0; g0 < nsrc || g0 == 0; g0 += std::max(g, 1)) {
+        const int ng = std::min(g, nsrc - g0);
+        const size_t o = (size_t)g0 * per_src;
+        if ((st = gradient_run(m, src ? src + g0 : src, ng, rec, nrec, chan_mask, freq_hz, nfreq,
+                               g_obs ? g_obs + o : nullptr, g_bar ? g_bar + o : nullptr, green ? green + o : nullptr,
+                               chi, grad, g0 > 0, stream)) != EMM_OK)
+            return st;
+    }
+    if (misfit) *misfit = chi;
+    m->info.src_group = g;
     return EMM_OK;
 }
 

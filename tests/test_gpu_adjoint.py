@@ -99,6 +99,22 @@ def test_compact_dt_eps_gradient_is_bitwise(emm):
     assert np.array_equal(g0, g1) and c0 == c1
 
 
+def test_source_groups_give_the_same_gradient(emm):
+    """emm_gradient over three sources in groups of one, two (2 + 1) and all
+    at once: the same gradient, misfit and Green's functions bit for bit (the
+    groups add in the order of a single sweep)."""
+    w, wo = _case(seed=39, nsrc=3, nt=160)
+    G_obs, _ = F.forward(wo)
+    out = []
+    for grp in (-1, 1, 2):
+        with emm.Model(w, src_group=grp) as m:
+            g, G, c = m.gradient(g_obs=G_obs)
+            out.append((g, G, c, m.info()["src_group"]))
+    assert [o[3] for o in out] == [3, 1, 2]
+    for g, G, c, _ in out[1:]:
+        assert np.array_equal(g, out[0][0]) and np.array_equal(G, out[0][1]) and c == out[0][2]
+
+
 def test_cotangent_entry_equals_misfit_entry(emm):
     w, wo = _case(seed=37, nt=200)
     G_obs, _ = F.forward(wo)
@@ -129,12 +145,13 @@ def test_torch_autograd_function(emm):
 @pytest.mark.slow
 def test_gradient_refuses_a_schedule_that_does_not_fit(emm):
     """8 sources of the 438 x 438 x 238 grid at 8th order over 18 800 steps
-    need more than 1 TB of checkpoints even with two levels: the planner
-    answers EMM_ERR_OOM (and says to run fewer sources) instead of
+    in one sweep (src_group = -1; the default would split them into groups
+    that fit) need more than 1 TB of checkpoints even with two levels: the
+    planner answers EMM_ERR_OOM (and says to run fewer sources) instead of
     allocating."""
     w = configs.large_marine(nt=18800, rd=4, nsrc=8)
     G = np.ones((8, len(w.receivers), 6, len(w.freqs)), dtype=np.complex128)
-    with emm.Model(w) as m:
+    with emm.Model(w, src_group=-1) as m:
         print("[gpu] gradient planning, large grid, 8 sources", flush=True)
         with pytest.raises(emm.EmmError) as e:
             m.gradient(g_obs=G)
