@@ -10,6 +10,7 @@ namespace emm {
 struct AdjParams {
     int n1, n2, n3, pitch, r, nb, nsrc;
     int kz;                       // z planes per thread block of the gathers
+    int tw;                       // tile width of the gathers: 64 (x 4 rows) or 32 (x 8 rows)
     int xt, yt, zc, nstencil;     // tiles along x, y, z chunks; xt * yt * zc * nsrc
     long long fstride;            // one source's field array (plane * n3)
     // inputs (filtered by the CPML reverse) and outputs of the gather,
@@ -17,6 +18,10 @@ struct AdjParams {
     const float *in1, *in2, *in3;
     float *out1, *out2, *out3;
     const float *ce1, *ce2, *ce3; // dt/eps
+    // optional compact dt/eps for the reverse of the H update (as StepParams)
+    const unsigned *cei;
+    const float *cet;
+    int ncet;
     float scale;                  // Et += ce * scale * curl (REV_H), Hb -= scale * curl (else)
     // transposed FD tables [n_d][2r] of this reverse half step
     const float *tx, *ty, *tz;

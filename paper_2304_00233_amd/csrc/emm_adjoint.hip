@@ -103,7 +103,7 @@ __global__ __launch_bounds__(AT) void adj_filter(const AdjParams p) {
 }
 
 // 2./3. transposed curl gathers, in the layout of the forward stencil
-// kernel: a 64 x 4 tile of columns per 256-thread block marching a
+// kernel: a TX x (256/TX) tile of columns per 256-thread block marching a
 // chunk of kz planes, x/y taps staged in LDS per plane (double-buffered,
 // one barrier per plane, the next plane's loads issued right after it),
 // z taps in a 2r-deep register queue.  Because the CPML reverse filter
@@ -112,18 +112,24 @@ __global__ __launch_bounds__(AT) void adj_filter(const AdjParams p) {
 // the own rows with the x halo, the y taps of components 1 and 3 over the
 // own columns with the y halo; every staged value is the filtered one (the
 // slab array T inside the slab of its axis, the field elsewhere, zero off
-// the update set on that axis).
-template <int R, bool REV_H>
+// the update set on that axis).  CI (reverse of the H update only): dt/eps
+// from the compact form, the table in LDS.
+template <int R, bool REV_H, bool CI, int TX>
 __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
-    constexpr int TY = kTileY, NT = kTileX * kTileY;
+    constexpr int NT = kTileX * kTileY, TY = NT / TX;
+    static_assert(TX * TY == NT && (TX & (TX - 1)) == 0, "tile of NT threads, power-of-two width");
     constexpr int L = 2 * R;
     constexpr int HL = REV_H ? R : R - 1;     // taps at q - HL .. q - HL + L - 1
-    constexpr int W = kTileX + L - 1;
+    constexpr int W = TX + L - 1;
     constexpr int HR = TY + L - 1;
     constexpr int NX = (TY * W + NT - 1) / NT;        // x-type staging loads per thread
-    constexpr int NY = (HR * kTileX + NT - 1) / NT;   // y-type staging loads per thread
+    constexpr int NY = (HR * TX + NT - 1) / NT;       // y-type staging loads per thread
     __shared__ float s3x[2][TY][W], s2x[2][TY][W];    // x taps of components 3 and 2
-    __shared__ float s3y[2][HR][kTileX], s1y[2][HR][kTileX];   // y taps of components 3 and 1
+    __shared__ float s3y[2][HR][TX], s1y[2][HR][TX];  // y taps of components 3 and 1
+    __shared__ float sCe[CI ? kCeTable : 1];
+    static_assert(kCeTable <= NT, "one table entry per thread");
+    // read only after the first barrier of the plane loop
+    if (CI && (int)threadIdx.x < p.ncet) sCe[threadIdx.x] = p.cet[threadIdx.x];
 
     int t = xcd_tile(blockIdx.x, p.nstencil);
     const int s = t % p.nsrc;
@@ -132,8 +138,8 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
     t /= p.xt;
     const int byt = t % p.yt;
     const int bzt = t / p.yt;
-    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-    const int i0 = bxt * kTileX, j0 = R + byt * TY;
+    const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
+    const int i0 = bxt * TX, j0 = R + byt * TY;
     const int i = i0 + tx, j = j0 + ty;
     const int k0 = R + bzt * p.kz, k1 = min(k0 + p.kz, p.n3 - R);
     const bool valid = i >= R && i <= p.n1 - 1 - R && j <= p.n2 - 1 - R;
@@ -176,9 +182,9 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
 #pragma unroll
     for (int u = 0; u < NY; ++u) {
         const int e = tid + u * NT;
-        const int ly = e >> 6, lx = e & 63;
+        const int ly = e / TX, lx = e & (TX - 1);
         const int gj = j0 - HL + ly, gi = i0 + lx;
-        const bool in = e < HR * kTileX && gj >= 0 && gj < p.n2 && on_set(gj, p.n2) && gi < p.pitch;
+        const bool in = e < HR * TX && gj >= 0 && gj < p.n2 && on_set(gj, p.n2) && gi < p.pitch;
         const int si = in ? slab(gj, p.n2) : -1;
         yo[u] = in ? gj * p.pitch + gi : -1;
         ys[u] = si >= 0 ? si * p.pitch + gi : -1;
@@ -204,6 +210,7 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
 
     float f3x[NX], f2x[NX], f3y[NY], f1y[NY], e1n = 0.f, e2n = 0.f;
     float o1 = 0.f, o2 = 0.f, o3 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
+    unsigned wi = 0;
     auto issue = [&](int k) {
         const int pk = k * plane;
 #pragma unroll
@@ -223,7 +230,9 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
             o1 = O1[g];
             o2 = O2[g];
             o3 = O3[g];
-            if (REV_H) {
+            if (REV_H && CI) {
+                wi = p.cei[g];
+            } else if (REV_H) {
                 w1 = p.ce1[g];
                 w2 = p.ce2[g];
                 w3 = p.ce3[g];
@@ -248,13 +257,20 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
             }
 #pragma unroll
         for (int u = 0; u < NY; ++u)
-            if (u < NY - 1 || tid + u * NT < HR * kTileX) {
+            if (u < NY - 1 || tid + u * NT < HR * TX) {
                 (&s3y[b][0][0])[tid + u * NT] = f3y[u];
                 (&s1y[b][0][0])[tid + u * NT] = f1y[u];
             }
-        const float u1 = o1, u2 = o2, u3 = o3, v1 = w1, v2 = w2, v3 = w3;
+        const float u1 = o1, u2 = o2, u3 = o3;
+        float v1 = w1, v2 = w2, v3 = w3;
+        const unsigned vi = wi;
         __syncthreads();
         if (k + 1 < k1) issue(k + 1);
+        if (CI) {
+            v1 = sCe[vi & 255u];
+            v2 = sCe[(vi >> 8) & 255u];
+            v3 = sCe[(vi >> 16) & 255u];
+        }
         if (valid) {
             const float *cz = p.tz + k * L;
             float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
@@ -347,20 +363,29 @@ void launch_adj_filter(bool rev_h, const AdjParams &p, hipStream_t st) {
     else hipLaunchKernelGGL(adj_filter<false>, grid, block, 0, st, p);
 }
 
-template <bool REV_H>
+template <bool REV_H, bool CI, int TX>
 static void tiled(int r, const AdjParams &p, hipStream_t st) {
     const dim3 grid(p.nstencil), block(kTileX * kTileY);
     switch (r) {
-    case 1: hipLaunchKernelGGL((adj_tile<1, REV_H>), grid, block, 0, st, p); break;
-    case 2: hipLaunchKernelGGL((adj_tile<2, REV_H>), grid, block, 0, st, p); break;
-    case 3: hipLaunchKernelGGL((adj_tile<3, REV_H>), grid, block, 0, st, p); break;
-    default: hipLaunchKernelGGL((adj_tile<4, REV_H>), grid, block, 0, st, p); break;
+    case 1: hipLaunchKernelGGL((adj_tile<1, REV_H, CI, TX>), grid, block, 0, st, p); break;
+    case 2: hipLaunchKernelGGL((adj_tile<2, REV_H, CI, TX>), grid, block, 0, st, p); break;
+    case 3: hipLaunchKernelGGL((adj_tile<3, REV_H, CI, TX>), grid, block, 0, st, p); break;
+    default: hipLaunchKernelGGL((adj_tile<4, REV_H, CI, TX>), grid, block, 0, st, p); break;
     }
 }
 
 void launch_adj_tile(int r, bool rev_h, const AdjParams &p, hipStream_t st) {
-    if (rev_h) tiled<true>(r, p, st);
-    else tiled<false>(r, p, st);
+    const bool w32 = p.tw == 32;
+    if (rev_h && p.cei) {
+        if (w32) tiled<true, true, 32>(r, p, st);
+        else tiled<true, true, 64>(r, p, st);
+    } else if (rev_h) {
+        if (w32) tiled<true, false, 32>(r, p, st);
+        else tiled<true, false, 64>(r, p, st);
+    } else {
+        if (w32) tiled<false, false, 32>(r, p, st);
+        else tiled<false, false, 64>(r, p, st);
+    }
 }
 
 void launch_adj_inject(const InjectParams &p, int n, hipStream_t st) {

@@ -2048,15 +2048,19 @@ emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm
     PE.r = r;
     PE.nb = nb;
     PE.nsrc = nsrc;
-    PE.kz = A.Pe.kz;                          // z chunks of the forward kernels, 64 x 4 tiles
-    PE.xt = m->pitch / emm::kTileX;
-    PE.yt = (n2 - 2 * r + emm::kTileY - 1) / emm::kTileY;
+    PE.kz = A.Pe.kz;                          // z chunks and tile width of the forward kernels
+    PE.tw = A.Pe.tx;
+    PE.xt = A.Pe.xt;
+    PE.yt = A.Pe.yt;
     PE.zc = A.Pe.zc;
     PE.nstencil = PE.xt * PE.yt * PE.zc * nsrc;
     PE.fstride = fstride;
     PE.ce1 = m->ce[0];
     PE.ce2 = m->ce[1];
     PE.ce3 = m->ce[2];
+    PE.cei = A.Pe.cei;                        // compact dt/eps when the forward used it
+    PE.cet = m->cet;
+    PE.ncet = m->ncet;
     PE.a_int = acp;
     PE.b_int = acp + nsum;
     PE.a_half = acp + 2 * nsum;

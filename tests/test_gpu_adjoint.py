@@ -99,6 +99,24 @@ def test_compact_dt_eps_gradient_is_bitwise(emm):
     assert np.array_equal(g0, g1) and c0 == c1
 
 
+@pytest.mark.parametrize("rd", [2, 4])
+def test_tile_widths_give_the_same_gradient(emm, rd):
+    """The forward and adjoint gathers on 32 x 8 or 64 x 4 column tiles, with
+    compact or FP32 dt/eps: the same gradient bit for bit."""
+    w, wo = _case(seed=40, nt=150, rd=rd, shape=(25, 23, 21), nb=5)
+    G_obs, _ = F.forward(wo)
+    out = []
+    for kw in (dict(tile_x=64, ce_table=0), dict(tile_x=32, ce_table=0), dict(tile_x=32, ce_table=1),
+               dict(tile_x=64, ce_table=1)):
+        with emm.Model(w, **kw) as m:
+            g, _, c = m.gradient(g_obs=G_obs)
+            i = m.info()
+            assert (i["tile_x"], i["ce_table"]) == (kw["tile_x"], kw["ce_table"])
+            out.append((g, c))
+    for g, c in out[1:]:
+        assert np.array_equal(g, out[0][0]) and c == out[0][1]
+
+
 def test_source_groups_give_the_same_gradient(emm):
     """emm_gradient over three sources in groups of one, two (2 + 1) and all
     at once: the same gradient, misfit and Green's functions bit for bit (the
