@@ -19,9 +19,10 @@
 // planes; on smaller grids plain accesses let the arrays stay resident
 // between steps.  The autotuner times both.
 //
-// Work decomposition: a 256-thread block covers a 64 (x) by 4 (y) tile of
-// columns and marches a chunk of z planes.  Each wavefront owns one 64-wide
-// row along x (coalesced 256-byte accesses).  Per plane, the x/y stencil
+// Work decomposition: a 256-thread block covers a 64 (x) by 4 (y) or a 32
+// by 8 tile of columns and marches a chunk of z planes.  A wavefront owns
+// one 64-wide row along x, or two 32-wide rows (coalesced 256- or 128-byte
+// accesses per row segment).  Per plane, the x/y stencil
 // operands are staged in LDS with their halos; the two z-differentiated
 // components live in a 2r-deep register queue per column, so every plane of
 // them is loaded once.  Tiles are mapped to the eight XCDs in contiguous
