@@ -92,18 +92,20 @@ def test_kahan_fp32_accumulators(emm):
     _, _, rep = _check(emm, w, "kahan", dft_mode=1)
 
 
-@pytest.mark.parametrize("rd", [2, 4])
+@pytest.mark.parametrize("rd", [1, 2, 3, 4])
 def test_bitwise_determinism_runs_and_tiles(emm, rd):
-    """Runs, z chunks and both tile widths (64 x 4 and 32 x 8 columns) give
-    the same results bit for bit."""
+    """Runs, z chunks, both tile widths (64 x 4 and 32 x 8 columns) and both
+    dt/eps forms give the same results bit for bit, at every stencil order."""
     w = configs.small_case(seed=9, shape=(40, 30, 37), nt=200, rd=rd)
     G1, _ = _run(emm, w)
     G2, _ = _run(emm, w)
     G3, i3 = _run(emm, w, tile_kz=3)
-    G4, i4 = _run(emm, w, tile_x=32, tile_kz=7)
-    G5, i5 = _run(emm, w, tile_x=64)
-    assert i3["tile_kz"] == 3 and (i4["tile_x"], i5["tile_x"]) == (32, 64)
-    for G in (G2, G3, G4, G5):
+    G4, i4 = _run(emm, w, tile_x=32, tile_kz=7, ce_table=1)
+    G5, i5 = _run(emm, w, tile_x=64, ce_table=0)
+    G6, i6 = _run(emm, w, tile_x=32, ce_table=0, nontemporal=1)
+    assert i3["tile_kz"] == 3 and (i4["tile_x"], i5["tile_x"], i6["tile_x"]) == (32, 64, 32)
+    assert (i4["ce_table"], i5["ce_table"], i6["ce_table"]) == (1, 0, 0)
+    for G in (G2, G3, G4, G5, G6):
         assert np.array_equal(G1, G)
 
 
