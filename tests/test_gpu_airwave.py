@@ -57,6 +57,16 @@ def test_air_boundary_batched_sources_bitwise(emm):
         assert np.array_equal(Gb[s:s + 1], Gs)
 
 
+def test_air_boundary_source_groups_bitwise(emm):
+    """Three sources in groups of 2 + 1 (the ghost-fill plans are rebuilt when
+    the group size changes) give the one-loop batch bit for bit."""
+    w = _air_case(54, (28, 26, 22), 2, 5, nsrc=3, nt=200)
+    G1, i1 = emm.forward_workload(w, src_group=-1)
+    G2, i2 = emm.forward_workload(w, src_group=2, graph_steps=16)
+    assert (i1["src_group"], i2["src_group"]) == (3, 2)
+    assert np.array_equal(G1, G2)
+
+
 def test_air_boundary_graph_replays_are_bitwise_identical(emm):
     """The ghost fills (hipFFT transforms and spectral kernels) captured in
     the step graphs and replayed 12 times per forward give the direct
