@@ -629,7 +629,7 @@ int source_group(const emm_model *m, int nsrc) {
     if (m->opt.src_group < 0) return nsrc;
     const double budget = 160.0 * (1 << 20);
     const double per = 4.0 * (double)state_floats(m);
-    const double shared = (double)m->pitch * m->np[1] * m->np[2] * (m->cei ? 4.0 : 12.0);
+    const double shared = (double)m->pitch * m->np[1] * m->np[2] * (choose_compact(m, nsrc) ? 4.0 : 12.0);
     if (per + shared > budget) return nsrc;
     return std::max(1, std::min(nsrc, (int)((budget - shared) / per)));
 }
