@@ -131,7 +131,28 @@ def multi_model_comparison(emm, graph: int):
         for m in models + [first_all]:
             m.close()
     same = all(np.array_equal(a, b) and np.array_equal(a, c) for a, b, c in zip(seq, bat, one))
-    return {"models": [w.name for w in ws], "sequential_s": t_seq, "batch_s": t_bat,
+    # eight small grids (74^3 padded), which one at a time leave most of the chip idle
+    small = [configs.uniform_cube(40, nt=640) for _ in range(8)]
+    sm = [emm.Model(w, graph_steps=graph) for w in small]
+    try:
+        for m in sm:
+            m.forward()
+        t = time.perf_counter()
+        for m in sm:
+            m.forward()
+        s_seq = time.perf_counter() - t
+        emm.forward_models(sm, graph_steps=graph)
+        t = time.perf_counter()
+        emm.forward_models(sm, graph_steps=graph)
+        s_bat = time.perf_counter() - t
+        s_grp = sm[0].info()["src_group"]
+    finally:
+        for m in sm:
+            m.close()
+    return {"small_models": {"models": "8 x uniform_cube_40 (74^3 padded), 640 steps",
+                             "sequential_s": s_seq, "batch_s": s_bat, "speedup": s_seq / s_bat,
+                             "jobs_per_graph": s_grp},
+            "models": [w.name for w in ws], "sequential_s": t_seq, "batch_s": t_bat,
             "jobs_per_graph": groups, "speedup": t_seq / t_bat, "all_in_one_graph_s": t_one,
             "speedup_all_in_one_graph": t_seq / t_one, "gcell_steps": cellsteps / 1e9,
             "batch_gcell_step_per_s": cellsteps / t_bat / 1e9, "bitwise_equal": same}

@@ -210,24 +210,26 @@ typedef struct {
 } emm_job;
 
 /* Run the forward modellings of njobs jobs on different models (any grid
- * sizes; each keeps its own dt, step count and autotuned tiles) as the
- * independent branches of one captured hipGraph of graph_steps time steps
- * per job (0 = 64), replayed with a device step counter per model: small
- * grids then share the chip instead of running one after another (the
- * paper runs one transmitter per process, Section 5; here many models and
- * sources share one launch stream).  When a job has done all its whole
- * graph_steps blocks, the graph is captured again without it and its last
- * nt % graph_steps steps run as direct launches.  Each job's green is
- * exactly what emm_forward writes for it (bitwise).  Jobs run in
- * consecutive groups, one graph per group, group after group, by the
- * src_group option of the first job's model: -1 = all jobs in one graph,
- * k > 0 = k jobs per graph, 0 = as many jobs as keep their arrays within
+ * sizes; each keeps its own dt, step count and autotuned tiles) side by
+ * side: each job gets its own stream and its own captured hipGraph of
+ * graph_steps time steps (0 = 64), replayed with a device step counter per
+ * model, and its last nt % graph_steps steps as direct launches; the
+ * replays of all jobs of a group are issued in turn, so small grids share
+ * the chip instead of running one after another (the paper runs one
+ * transmitter per process, Section 5; here many models and sources share one
+ * device).  Each job's green is exactly what emm_forward writes for it
+ * (bitwise).  Jobs run in consecutive groups, group after group, by the
+ * src_group option of the first job's model: -1 = all jobs together,
+ * k > 0 = k jobs per group, 0 = as many jobs as keep their arrays within
  * 160 MiB (the Infinity Cache rule of emm_forward; a job that alone exceeds
- * it runs by itself); info.src_group of each model then holds the number of
- * jobs in its graph.  A model may appear in
- * one job only; every model must live on the same device.  hip_stream: as
- * emm_forward (NULL = the first model's stream).  Errors: as emm_forward;
- * the first failing job stops the call (emm_last_error of that model). */
+ * it runs by itself), except that a group takes more jobs while its grids
+ * hold fewer than 4 Mi cells in all (too few to fill the chip);
+ * info.src_group of each model then holds the number of jobs in its group.
+ * A model may appear in one job only; every model must live on the same
+ * device.  hip_stream: the work starts after what is queued on it and it
+ * waits for all jobs (NULL = the first model's stream).  Errors: as
+ * emm_forward; the first failing job stops the call (emm_last_error of that
+ * model). */
 emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, void *hip_stream);
 
 /* Discrete adjoint of the whole time loop (the exact gradient of the

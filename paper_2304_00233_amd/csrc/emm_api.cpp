@@ -1457,12 +1457,13 @@ emm_status write_green(emm_model *m, hipStream_t stream, double *green) {
     return EMM_OK;
 }
 
-// Time loops of several models (one job each) in one captured hipGraph: the
-// K-step sequences of the jobs are independent branches of the graph, so
-// small grids run side by side on the chip.  Jobs have their own dt and step
-// count; the graph is re-captured for the jobs still running whenever one
-// has done all its whole K-step blocks, and that job's last nt % K steps run
-// as direct launches.
+// Time loops of several models (one job each) side by side: every job has
+// its own stream and its own captured hipGraph of K steps (replayed with the
+// model's device step counter), the replays of all jobs are issued in turn,
+// and a job's last nt % K steps run as direct launches on its stream.  The
+// jobs' streams start after the work already queued on `stream` and
+// `stream` waits for all of them at the end, so small grids share the chip
+// (eight 74^3 grids: 2.4x faster than one after another).
 emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t stream) {
     emm_status st = EMM_OK;
     emm_model *m0 = ms[0];
@@ -1475,79 +1476,59 @@ emm_status time_loop_jobs(const std::vector<emm_model *> &ms, int K, hipStream_t
     }
     std::vector<hipStream_t> side(nj, nullptr);
     std::vector<hipEvent_t> join(nj, nullptr);
+    std::vector<hipGraph_t> graph(nj, nullptr);
+    std::vector<hipGraphExec_t> exec(nj, nullptr);
     hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
     auto cleanup = [&]() {
+        for (hipStream_t q : side) if (q) (void)hipStreamSynchronize(q);
+        for (hipGraphExec_t x : exec) if (x) (void)hipGraphExecDestroy(x);
+        for (hipGraph_t g : graph) if (g) (void)hipGraphDestroy(g);
         for (hipStream_t q : side) if (q) (void)hipStreamDestroy(q);
         for (hipEvent_t e : join) if (e) (void)hipEventDestroy(e);
         for (hipEvent_t e : {fork, t0, t1}) if (e) (void)hipEventDestroy(e);
     };
     auto run = [&]() -> emm_status {
-        for (int j = 0; j < nj; ++j) {
-            HIP_OK(m0, hipStreamCreateWithFlags(&side[j], hipStreamNonBlocking));
-            HIP_OK(m0, hipEventCreateWithFlags(&join[j], hipEventDisableTiming));
-        }
         HIP_OK(m0, hipEventCreateWithFlags(&fork, hipEventDisableTiming));
         HIP_OK(m0, hipEventCreate(&t0));
         HIP_OK(m0, hipEventCreate(&t1));
-        HIP_OK(m0, hipEventRecord(t0, stream));
         std::vector<int> whole(nj);
-        for (int j = 0; j < nj; ++j) whole[j] = ms[j]->acq.nt / K;
-        int q = 0;                                    // K-step blocks done by every running job
-        std::vector<bool> done(nj, false);
-        for (;;) {
-            // finish the jobs whose whole blocks are done: their remainder steps
-            for (int j = 0; j < nj; ++j) {
-                if (done[j] || whole[j] > q) continue;
-                const Acq &A = ms[j]->acq;
-                for (int n = whole[j] * K; n < A.nt; ++n) {
-                    emm::launch_e_step(ms[j]->r, A.Pe, n, stream);
-                    emm::launch_h_step(ms[j]->r, A.Ph, n, stream);
-                }
-                done[j] = true;
+        int most = 0;
+        for (int j = 0; j < nj; ++j) {
+            HIP_OK(m0, hipStreamCreateWithFlags(&side[j], hipStreamNonBlocking));
+            HIP_OK(m0, hipEventCreateWithFlags(&join[j], hipEventDisableTiming));
+            emm_model *m = ms[j];
+            whole[j] = m->acq.nt / K;
+            most = std::max(most, whole[j]);
+            if (whole[j] == 0) continue;
+            emm::StepParams Pe = m->acq.Pe, Ph = m->acq.Ph;
+            Pe.step_base = Ph.step_base = (const int *)m->stepdev.p;
+            HIP_OK(m0, hipStreamBeginCapture(side[j], hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < K; ++i) {
+                emm::launch_e_step(m->r, Pe, i, side[j]);
+                emm::launch_h_step(m->r, Ph, i, side[j]);
             }
-            int reps = INT32_MAX;
-            std::vector<int> act;
+            emm::launch_advance((int *)m->stepdev.p, K, side[j]);
+            hipError_t ce = hipStreamEndCapture(side[j], &graph[j]);
+            if (ce != hipSuccess) return fail(m0, EMM_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+            ce = hipGraphInstantiate(&exec[j], graph[j], nullptr, nullptr, 0);
+            if (ce != hipSuccess)
+                return fail(m0, EMM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ce));
+        }
+        // the jobs start after what is queued on `stream` (state set-up)
+        HIP_OK(m0, hipEventRecord(t0, stream));
+        HIP_OK(m0, hipEventRecord(fork, stream));
+        for (int j = 0; j < nj; ++j) HIP_OK(m0, hipStreamWaitEvent(side[j], fork, 0));
+        for (int u = 0; u < most; ++u)
             for (int j = 0; j < nj; ++j)
-                if (!done[j]) {
-                    act.push_back(j);
-                    reps = std::min(reps, whole[j] - q);
-                }
-            if (act.empty()) break;
-            hipGraph_t graph = nullptr;
-            hipGraphExec_t exec = nullptr;
-            HIP_OK(m0, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-            hipError_t ce = hipEventRecord(fork, stream);
-            for (int j : act) {
-                if (ce != hipSuccess) break;
-                emm_model *m = ms[j];
-                emm::StepParams Pe = m->acq.Pe, Ph = m->acq.Ph;
-                Pe.step_base = Ph.step_base = (const int *)m->stepdev.p;
-                ce = hipStreamWaitEvent(side[j], fork, 0);
-                for (int i = 0; i < K && ce == hipSuccess; ++i) {
-                    emm::launch_e_step(m->r, Pe, i, side[j]);
-                    emm::launch_h_step(m->r, Ph, i, side[j]);
-                }
-                emm::launch_advance((int *)m->stepdev.p, K, side[j]);
-                if (ce == hipSuccess) ce = hipEventRecord(join[j], side[j]);
-                if (ce == hipSuccess) ce = hipStreamWaitEvent(stream, join[j], 0);
+                if (u < whole[j]) HIP_OK(m0, hipGraphLaunch(exec[j], side[j]));
+        for (int j = 0; j < nj; ++j) {
+            const Acq &A = ms[j]->acq;
+            for (int n = whole[j] * K; n < A.nt; ++n) {
+                emm::launch_e_step(ms[j]->r, A.Pe, n, side[j]);
+                emm::launch_h_step(ms[j]->r, A.Ph, n, side[j]);
             }
-            hipError_t ee = hipStreamEndCapture(stream, &graph);
-            if (ce != hipSuccess || ee != hipSuccess) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return fail(m0, EMM_ERR_DEVICE, std::string("graph capture: ") +
-                                                    hipGetErrorString(ce != hipSuccess ? ce : ee));
-            }
-            hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                return fail(m0, EMM_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-            }
-            for (int u = 0; u < reps && e == hipSuccess; ++u) e = hipGraphLaunch(exec, stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(stream);
-            (void)hipGraphExecDestroy(exec);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) return fail(m0, EMM_ERR_DEVICE, std::string("graph replay: ") + hipGetErrorString(e));
-            q += reps;
+            HIP_OK(m0, hipEventRecord(join[j], side[j]));
+            HIP_OK(m0, hipStreamWaitEvent(stream, join[j], 0));
         }
         HIP_OK(m0, hipGetLastError());
         HIP_OK(m0, hipEventRecord(t1, stream));
@@ -1748,8 +1729,9 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
     // budget of source_group; a job that alone exceeds it runs by itself)
     const int rule = ms[0]->opt.src_group;
     const double budget = 160.0 * (1 << 20);
+    const double fill = 4.0 * (1 << 20);             // cells that keep the chip busy on their own
     std::vector<emm_model *> group;
-    double held = 0.0;
+    double held = 0.0, cells = 0.0;
     for (int j = 0; j <= njobs; ++j) {
         double need = 0.0;
         if (j < njobs) {
@@ -1757,16 +1739,21 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
             need = 4.0 * (double)state_floats(m) * jobs[j].nsrc +
                    (double)m->pitch * m->np[1] * m->np[2] * (m->acq.Pe.cei ? 4.0 : 12.0);
         }
-        const bool full = rule < 0 ? false : rule > 0 ? (int)group.size() == rule : held + need > budget;
+        // a group closes when the next job would overflow the cache budget,
+        // unless the group is still too small to fill the chip
+        const bool full = rule < 0 ? false
+                          : rule > 0 ? (int)group.size() == rule
+                                     : held + need > budget && cells >= fill;
         if (!group.empty() && (j == njobs || full)) {
             if ((st = time_loop_jobs(group, graph_steps > 0 ? graph_steps : 64, stream)) != EMM_OK) return st;
             for (emm_model *m : group) m->info.src_group = (int)group.size();
             group.clear();
-            held = 0.0;
+            held = cells = 0.0;
         }
         if (j < njobs) {
             group.push_back(ms[j]);
             held += need;
+            cells += (double)ms[j]->np[0] * ms[j]->np[1] * ms[j]->np[2] * jobs[j].nsrc;
         }
     }
     for (int j = 0; j < njobs; ++j)
