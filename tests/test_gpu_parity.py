@@ -170,6 +170,9 @@ def test_fused_step_equals_half_steps(emm, kw):
     assert (i0["fused"], i1["fused"], i2["fused"]) == (0, 1, 1)
     assert np.array_equal(G0, G1)
     assert np.array_equal(G0, G2)
+    if len(w.sources) > 1:                    # one fused time loop per source
+        G3, i3 = _run(emm, w, fused=1, src_group=1)
+        assert i3["src_group"] == 1 and np.array_equal(G0, G3)
 
 
 def test_nontemporal_hint_is_bitwise_neutral(emm):
@@ -235,8 +238,18 @@ def test_multi_model_batch_equals_single_forwards(emm):
     for a, b, c in zip(outs, singles, outs1):
         assert np.array_equal(a, b) and np.array_equal(c, b)
     assert [i["nt"] for i in infos] == [150, 230, 100]
-    assert [i["src_group"] for i in infos] == [3, 3, 3]      # small grids share one graph
+    assert [i["src_group"] for i in infos] == [3, 3, 3]      # small grids share one group
     assert [i["src_group"] for i in infos1] == [1, 1, 1]
+    # graphs of 200 steps: two jobs are shorter (direct launches only)
+    models = [emm.Model(w) for w in ws]
+    try:
+        print("[gpu] forward_models of 3 models, 200-step graphs", flush=True)
+        outs2 = emm.forward_models(models, graph_steps=200)
+    finally:
+        for m in models:
+            m.close()
+    for a, b in zip(outs2, singles):
+        assert np.array_equal(a, b)
     G_o, _ = F.forward(ws[1])
     rep = compare(outs[1], G_o, ws[1].channels)
     print(f"[parity] multi-model job 1: {rep}", flush=True)
