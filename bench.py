@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import subprocess
 import os
 import sys
 import time
@@ -50,6 +51,28 @@ def cpu_baseline(w, nt_sample: int):
             "kind": "oracle",
             "sample": f"{w.name}, first {nt_sample} time steps, FP64 C/OpenMP oracle, "
                       f"{dt:.1f} s wall"}
+
+
+def stream_reference(reps: int = 20):
+    """A plain streaming rate measured on this GPU: torch's device copy of a
+    1 GiB array (read + write), timed with events after a warm-up."""
+    import torch
+    a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    sec = t0.elapsed_time(t1) / 1e3 / reps
+    nbytes = 2 * a.numel() * 4
+    del a, b
+    torch.cuda.empty_cache()
+    return {"kernel": "device copy of 1 GiB (torch copy_)", "GBs": nbytes / sec / 1e9}
 
 
 def batched_comparison(emm, w, nsrc: int, group: int, ckpt: int):
@@ -236,7 +259,12 @@ def main():
                          "the adjoint) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
+    ap.add_argument("--stream-reference", action="store_true",
+                    help="print the device-copy rate of this GPU as JSON and exit")
     args = ap.parse_args()
+    if args.stream_reference:
+        print(json.dumps(stream_reference()))
+        return
     if args.copy_calibration:
         import torch
         a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
@@ -266,6 +294,19 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by "
               "source with no communication between GPUs", file=sys.stderr)
         sys.exit(2)
+
+    # the streaming reference runs in a child process before this one touches
+    # the GPU (torch brings its own HIP runtime, which cannot share a process
+    # with the library's)
+    stream_ref = None
+    try:
+        log("[bench] stream reference (1 GiB device copy, child process)")
+        res = subprocess.run([sys.executable, os.path.abspath(__file__), "--stream-reference"],
+                             capture_output=True, text=True, timeout=300)
+        if res.returncode == 0:
+            stream_ref = json.loads(res.stdout.strip().splitlines()[-1])
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        stream_ref = None
 
     from paper_2304_00233_amd import emm
     from workloads import configs
@@ -353,6 +394,9 @@ def main():
     if not fused:
         out["h_step"] = {"bytes_per_launch": info["h_bytes"], "avg_launch_us": h_avg_s * 1e6,
                          "achieved_GBs": info["h_bytes"] / h_avg_s / 1e9}
+    if stream_ref:
+        out["stream_reference"] = dict(stream_ref)
+        out["stream_reference"]["e_step_frac_of_it"] = achieved / stream_ref["GBs"]
     if args.batched and args.workload == "marine":
         log(f"[bench] batched comparison with {args.batched} sources")
         out["batched"] = batched_comparison(emm, w, args.batched, args.grad_group, args.grad_ckpt)
