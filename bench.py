@@ -386,6 +386,10 @@ def main():
                      if args.workload == "marine" else None,
                      "bytes_per_launch": kbytes, "avg_launch_us": e_avg_s * 1e6},
         "device_loop_ms_per_step": dev_ms / args.steps,
+        # the same run counted over the model's interior nodes only (the
+        # padding of nb + ne cells per face is streamed too, so `value`
+        # counts it)
+        "interior_gcell_step_per_s": (len(w.x1) * len(w.x2) * len(w.x3)) * nt * args.steps / wall / 1e9,
         "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"],
                    "nontemporal": info["nontemporal"], "compact_dt_eps": info["ce_table"],
                    "graph_steps": args.graph},
