@@ -39,6 +39,12 @@ class AirBoundary {
     int nbin_ = 0;                       // n2 * (n1/2 + 1)
     hipfftHandle fwdE_ = 0, fwdH_ = 0, invE_ = 0, invH_ = 0;
     bool have_fwdE_ = false, have_fwdH_ = false, have_invE_ = false, have_invH_ = false;
+    // inverse transforms of all ghost planes of a fill in one execution, into
+    // ghost_ (planes [m - 1][component][source], rows `pitch` apart), then one
+    // scatter kernel; used when a fill has more than one plane per component
+    hipfftHandle invEall_ = 0, invHall_ = 0;
+    bool have_invEall_ = false, have_invHall_ = false;
+    float *ghost_ = nullptr;
     float2 *spec_ = nullptr, *work_ = nullptr;
     float *decE_ = nullptr;              // [r-1][nbin] exp(-|k| h) / (n1 n2)
     float2 *rx_ = nullptr, *ry_ = nullptr;   // [r][nbin]

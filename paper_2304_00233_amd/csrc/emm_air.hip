@@ -9,9 +9,11 @@
 //     Hy^ = i ky/|k| Hz^, times exp(-|k| h), with the half-cell shift of H1
 //     (x) and H2 (y) relative to H3 as a phase (the k = 0 mode is 0).
 // Transforms: batched 2-D real-to-complex and complex-to-real FFTs (hipFFT)
-// over the whole padded x-y plane, which must have uniform spacing.  Each
-// inverse transform writes one ghost plane of all sources and both
-// components (their arrays are one field stride apart).
+// over the whole padded x-y plane, which must have uniform spacing.  With
+// one ghost plane per component, the inverse transform writes it for all
+// sources and both components directly (their arrays are one field stride
+// apart); with more, one inverse execution covers every ghost plane of the
+// fill into a scratch buffer and one kernel scatters them.
 #include "emm_air.h"
 
 #include <cmath>
@@ -52,6 +54,20 @@ __global__ __launch_bounds__(AT) void air_mul_h(const float2 *S, float2 *W, cons
     W[t] = make_float2(v.x * f.x - v.y * f.y, v.x * f.y + v.y * f.x);
 }
 
+// ghost plane o of the scratch (o = (m - 1) * 2 nsrc + a, a = component *
+// nsrc + source) into plane ks - m of field array a; n1 of the pitch columns
+__global__ __launch_bounds__(AT) void air_scatter(const float *G, float *F, long long fstride, long long plane,
+                                                   int ks, int two_ns, int n1, int n2, int pitch, int nplanes) {
+    const long long t = (long long)blockIdx.x * AT + threadIdx.x;
+    const long long per = (long long)n2 * n1;
+    if (t >= per * nplanes) return;
+    const int o = (int)(t / per);
+    const long long u = t - (long long)o * per;
+    const int y = (int)(u / n1), x = (int)(u - (long long)y * n1);
+    const int a = o % two_ns, m = o / two_ns + 1;
+    F[a * fstride + (ks - m) * plane + (long long)y * pitch + x] = G[((long long)o * n2 + y) * pitch + x];
+}
+
 unsigned blocks(long long n) { return (unsigned)((n + AT - 1) / AT); }
 
 const char *fft_name(hipfftResult r) {
@@ -74,7 +90,9 @@ AirBoundary::~AirBoundary() {
     if (have_fwdH_) (void)hipfftDestroy(fwdH_);
     if (have_invE_) (void)hipfftDestroy(invE_);
     if (have_invH_) (void)hipfftDestroy(invH_);
-    for (void *p : {(void *)spec_, (void *)work_, (void *)decE_, (void *)rx_, (void *)ry_})
+    if (have_invEall_) (void)hipfftDestroy(invEall_);
+    if (have_invHall_) (void)hipfftDestroy(invHall_);
+    for (void *p : {(void *)spec_, (void *)work_, (void *)decE_, (void *)rx_, (void *)ry_, (void *)ghost_})
         if (p) (void)hipFree(p);
 }
 
@@ -100,6 +118,21 @@ bool AirBoundary::init(const AirSpec &spec, std::string &err) {
     if (!plan(fwdE_, have_fwdE_, HIPFFT_R2C, 2 * ns) || !plan(fwdH_, have_fwdH_, HIPFFT_R2C, ns) ||
         !plan(invE_, have_invE_, HIPFFT_C2R, 2 * ns) || !plan(invH_, have_invH_, HIPFFT_C2R, 2 * ns))
         return false;
+    // all ghost planes of a fill at once, into the scratch planes
+    auto plan_all = [&](hipfftHandle &h, bool &have, int batch) -> bool {
+        int n[2] = {n2, n1};
+        int real_emb[2] = {n2, s_.pitch};
+        int cplx_emb[2] = {n2, n1h};
+        hipfftResult e = hipfftPlanMany(&h, 2, n, cplx_emb, 1, nbin_, real_emb, 1, n2 * s_.pitch, HIPFFT_C2R, batch);
+        if (e != HIPFFT_SUCCESS) {
+            err = std::string("hipfftPlanMany: ") + fft_name(e);
+            return false;
+        }
+        have = true;
+        return true;
+    };
+    if (r - 1 > 1 && !plan_all(invEall_, have_invEall_, (r - 1) * 2 * ns)) return false;
+    if (r > 1 && !plan_all(invHall_, have_invHall_, r * 2 * ns)) return false;
     // spectral factors in FP64, stored in FP32 with the 1/(n1 n2) of the inverse
     const double norm = 1.0 / ((double)n1 * n2);
     const double pi = 3.14159265358979323846;
@@ -138,6 +171,8 @@ bool AirBoundary::init(const AirSpec &spec, std::string &err) {
     if (e == hipSuccess) e = hipMalloc(&decE_, dec.size() * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&rx_, fx.size() * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc(&ry_, fy.size() * sizeof(float2));
+    if (e == hipSuccess && r > 1)
+        e = hipMalloc(&ghost_, (size_t)r * 2 * ns * n2 * s_.pitch * sizeof(float));
     if (e == hipSuccess) e = hipMemcpy(decE_, dec.data(), dec.size() * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(rx_, fx.data(), fx.size() * sizeof(float2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ry_, fy.data(), fy.size() * sizeof(float2), hipMemcpyHostToDevice);
@@ -160,9 +195,18 @@ bool AirBoundary::fill_E(float *E1, hipStream_t st, std::string &err) {
     }
     const long long total = (long long)(r - 1) * 2 * ns * nbin_;
     hipLaunchKernelGGL(air_mul_e, dim3(blocks(total)), dim3(AT), 0, st, spec_, work_, decE_, nbin_, 2 * ns, r - 1);
-    for (int m = 1; m < r && f == HIPFFT_SUCCESS; ++m)
-        f = hipfftExecC2R(invE_, (hipfftComplex *)(work_ + (size_t)(m - 1) * 2 * ns * nbin_),
-                          E1 + (long long)(s_.ks - m) * s_.plane);
+    if (have_invEall_) {
+        f = hipfftSetStream(invEall_, st);
+        if (f == HIPFFT_SUCCESS) f = hipfftExecC2R(invEall_, (hipfftComplex *)work_, ghost_);
+        const long long cells = (long long)(r - 1) * 2 * ns * s_.n2 * s_.n1;
+        if (f == HIPFFT_SUCCESS)
+            hipLaunchKernelGGL(air_scatter, dim3(blocks(cells)), dim3(AT), 0, st, ghost_, E1, s_.fstride, s_.plane,
+                               s_.ks, 2 * ns, s_.n1, s_.n2, s_.pitch, (r - 1) * 2 * ns);
+    } else {
+        for (int m = 1; m < r && f == HIPFFT_SUCCESS; ++m)
+            f = hipfftExecC2R(invE_, (hipfftComplex *)(work_ + (size_t)(m - 1) * 2 * ns * nbin_),
+                              E1 + (long long)(s_.ks - m) * s_.plane);
+    }
     if (f != HIPFFT_SUCCESS) {
         err = std::string("air boundary E inverse: ") + fft_name(f);
         return false;
@@ -182,9 +226,18 @@ bool AirBoundary::fill_H(float *H1, const float *H3, hipStream_t st, std::string
     }
     const long long total = (long long)r * 2 * ns * nbin_;
     hipLaunchKernelGGL(air_mul_h, dim3(blocks(total)), dim3(AT), 0, st, spec_, work_, rx_, ry_, nbin_, ns, r);
-    for (int m = 1; m <= r && f == HIPFFT_SUCCESS; ++m)
-        f = hipfftExecC2R(invH_, (hipfftComplex *)(work_ + (size_t)(m - 1) * 2 * ns * nbin_),
-                          H1 + (long long)(s_.ks - m) * s_.plane);
+    if (have_invHall_) {
+        f = hipfftSetStream(invHall_, st);
+        if (f == HIPFFT_SUCCESS) f = hipfftExecC2R(invHall_, (hipfftComplex *)work_, ghost_);
+        const long long cells = (long long)r * 2 * ns * s_.n2 * s_.n1;
+        if (f == HIPFFT_SUCCESS)
+            hipLaunchKernelGGL(air_scatter, dim3(blocks(cells)), dim3(AT), 0, st, ghost_, H1, s_.fstride, s_.plane,
+                               s_.ks, 2 * ns, s_.n1, s_.n2, s_.pitch, r * 2 * ns);
+    } else {
+        for (int m = 1; m <= r && f == HIPFFT_SUCCESS; ++m)
+            f = hipfftExecC2R(invH_, (hipfftComplex *)(work_ + (size_t)(m - 1) * 2 * ns * nbin_),
+                              H1 + (long long)(s_.ks - m) * s_.plane);
+    }
     if (f != HIPFFT_SUCCESS) {
         err = std::string("air boundary H inverse: ") + fft_name(f);
         return false;
