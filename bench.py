@@ -132,7 +132,7 @@ def multi_model_comparison(emm, graph: int):
     ws = configs.batched_models()
     models = [emm.Model(w, tile_kz=-1, graph_steps=graph) for w in ws]
     # the same first model with src_group = -1: as the first job it puts
-    # every job into one graph
+    # every job into one group (all side by side)
     first_all = emm.Model(ws[0], tile_kz=-1, graph_steps=graph, src_group=-1)
     try:
         for m in models + [first_all]:                         # tune + warm

@@ -254,8 +254,8 @@ def emm_forward_batch(jobs, graph_steps: int = 64, stream=None) -> list:
 
 
 def forward_models(models, graph_steps: int = 64, stream=None) -> list:
-    """Forward of several Model objects (their workloads' acquisitions) in
-    one hipGraph."""
+    """Forward of several Model objects (their workloads' acquisitions) side
+    by side (emm_forward_batch: each job its own stream and step graph)."""
     jobs = [(m.h, m.w.sources, m.w.receivers, m.w.chan_mask, m.w.freqs, m.w.src_comp)
             for m in models]
     return emm_forward_batch(jobs, graph_steps, stream)
