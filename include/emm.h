@@ -37,12 +37,14 @@ typedef struct emm_model emm_model;   /* opaque; owned by the caller between cre
 typedef enum {
     EMM_OK            =  0,
     EMM_ERR_ARG       = -1,  /* NULL pointer, count out of range, bad option, bad channel mask */
-    EMM_ERR_GRID      = -2,  /* n_d < 2*rd+1 or coordinates not finite / not strictly increasing */
+    EMM_ERR_GRID      = -2,  /* n_d < 2*rd+1, coordinates not finite / not strictly increasing, or
+                                a padded field array of 2^31 cells or more (see emm_create) */
     EMM_ERR_MODEL     = -3,  /* a resistivity <= 0 or not finite */
     EMM_ERR_GEOMETRY  = -4,  /* a source/receiver 2*rd stencil leaves the unpadded interior */
     EMM_ERR_FREQ      = -5,  /* a frequency <= 0 or not finite, or nfreq < 1 */
     EMM_ERR_CFL       = -6,  /* dt_override > 1/eta without allow_unstable */
-    EMM_ERR_NONFINITE = -7,  /* a DTFT accumulator ended non-finite (unstable run) */
+    EMM_ERR_NONFINITE = -7,  /* a DTFT accumulator ended non-finite (unstable run), or a misfit /
+                                cotangent of emm_gradient is not finite */
     EMM_ERR_OOM       = -8,  /* device memory request larger than what is free */
     EMM_ERR_DEVICE    = -9   /* a HIP call failed; emm_last_error() has the HIP message */
 } emm_status;
@@ -166,19 +168,31 @@ typedef struct {
     int    tile_x;           /* columns per block of the last forward's stencil kernels */
 } emm_info;
 
-/* Fill *o with the defaults above. */
+/* Fill *o with the defaults above: the paper's values where it states them
+ * (rd = 2, the order of its GPU code, Section 4; dt = 0.99/eta, Section 3.2;
+ * the CPML form of Section 3.4), this library's readings where it is silent
+ * (f0 of Section 2.2, the wavelet, the CPML constants).  Errors: ARG (o is
+ * NULL). */
 emm_status emm_default_options(emm_options *o);
 
-/* Validate the mesh and model, build the padded grid (Section 3.4: nb + ne
- * layers per side, coordinates extended with the end interval, resistivity
- * replicated), the FD coefficient tables by solving the transposed
- * Vandermonde system (Section 3.1, Bjorck-Pereyra), dt (Section 3.2) and
- * dt/eps per cell, then allocate device memory and upload.  On success *out
- * owns device memory until emm_destroy.  Errors: ARG, GRID, MODEL, CFL, OOM,
- * DEVICE; on error *out is NULL. */
+/* The set-up half of the init/close pairing of Section 3.8 (every module has
+ * an xxx_init that allocates and an xxx_close that frees; Algorithm 1
+ * set-up phase).  Validate the mesh and model, build the padded grid
+ * (Section 3.4: nb + ne layers per side, coordinates extended with the end
+ * interval, resistivity replicated), the FD coefficient tables by solving the
+ * transposed Vandermonde system (Section 3.1, Bjorck-Pereyra), dt
+ * (Section 3.2) and dt/eps per cell, then allocate device memory and upload.
+ * Size limit: one field array of the padded grid, (n1 + 2(nb+ne) rounded up
+ * to a multiple of 64) x (n2 + 2(nb+ne)) x (n3 + 2(nb+ne)) cells, must stay
+ * below 2^31 (the kernels use 32-bit offsets within it), else EMM_ERR_GRID
+ * before the resistivity arrays are read.  On success *out owns device memory
+ * until emm_destroy.  Errors: ARG, GRID, MODEL, CFL, OOM, DEVICE; on error
+ * *out is NULL. */
 emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out);
 
-/* Copy model facts into *info. Errors: ARG. */
+/* Copy model facts into *info: the padded grid (Section 3.4), dt
+ * (Section 3.2), the step count of the last forward (Section 3.5) and the
+ * launch and timing facts of the last run.  Errors: ARG. */
 emm_status emm_query(const emm_model *m, emm_info *info);
 
 /* Run the forward modelling for nsrc independent sources (batched in one
@@ -187,7 +201,8 @@ emm_status emm_query(const emm_model *m, emm_info *info);
  * for the channels c enumerated in bit order of chan_mask (bit 0..5 =
  * Ex, Ey, Ez, Hx, Hy, Hz; the order of the paper's output listing,
  * Section 5): G^EE in V/(A m^2) for E channels, G^HE in 1/m^2 for H
- * channels.  green must hold 2*nsrc*nrec*popcount(chan_mask)*nfreq doubles.
+ * channels.  green must hold 2*nsrc*nrec*popcount(chan_mask)*nfreq doubles;
+ * any number nfreq >= 1 of frequencies (Section 3.5: one DTFT each).
  * hip_stream: a hipStream_t to run on, or NULL for the library's own stream.
  * Errors: ARG, GEOMETRY, FREQ, NONFINITE, OOM, DEVICE. */
 emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc,
@@ -273,14 +288,17 @@ emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc,
                         const double *g_bar, double *green, double *misfit,
                         double *grad, void *hip_stream);
 
-/* Free device and host memory. NULL-safe. */
+/* The close half of the init/close pairing of Section 3.8: free the device
+ * and host memory emm_create and the runs allocated. NULL-safe. */
 void emm_destroy(emm_model *m);
 
-/* Static name of a status code. */
+/* Static name of a status code (the input classes of the problem statement
+ * of Section 5: grid, model, geometry, frequencies; plus run-time failures). */
 const char *emm_status_str(emm_status s);
 
-/* Detail of the last failure on this thread (validation message or HIP error
- * string); empty if none.  m may be NULL. */
+/* Detail of the last failure on this thread (a validation message naming
+ * the offending input of Section 5, or the HIP error string); empty if none.
+ * m may be NULL. */
 const char *emm_last_error(const emm_model *m);
 
 #ifdef __cplusplus

@@ -366,6 +366,15 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
         if (opt.nb + opt.ne < opt.rd)
             return fail(nullptr, EMM_ERR_GRID, "the air boundary needs nb + ne >= rd planes above the surface");
     }
+    {
+        // the kernels address one source's field array with 32-bit offsets:
+        // (n1 + 2 nbe, rounded up to 64) (n2 + 2 nbe) (n3 + 2 nbe) < 2^31
+        const long long nbe2 = 2LL * (opt.nb + opt.ne);
+        const long long pitch = (nd[0] + nbe2 + emm::kTileX - 1) / emm::kTileX * emm::kTileX;
+        if (pitch * (nd[1] + nbe2) * (nd[2] + nbe2) > (long long)INT32_MAX)
+            return fail(nullptr, EMM_ERR_GRID, "padded grid has more than 2^31 - 1 cells per field array "
+                                               "(x rows padded to a multiple of 64)");
+    }
     const long long ncell = (long long)nd[0] * nd[1] * nd[2];
     for (int a = 0; a < 3; ++a)
         for (long long c = 0; c < ncell; ++c)
@@ -1829,7 +1838,7 @@ emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm
     // L = 1/2 sum |log(G/G_obs)|^2, gbar = r / conj(G), r = log(G/G_obs).
     std::vector<double2> Acoef(nd);
     double chi = accumulate ? chi_acc : 0.0;
-    bool nonfinite = false;
+    bool nonfinite = false, badcot = false;
     for (size_t k = 0; k < nd; ++k) {
         const std::complex<double> c = green_factor(m, k);
         const std::complex<double> G = acc[k] * c;
@@ -1848,9 +1857,13 @@ emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm
             gb = {g_bar[2 * k], g_bar[2 * k + 1]};
         }
         const std::complex<double> a = std::conj(gb) * c;
+        if (!std::isfinite(a.real()) || !std::isfinite(a.imag())) badcot = true;
         Acoef[k] = make_double2(a.real(), a.imag());
     }
     if (nonfinite) return fail(m, EMM_ERR_NONFINITE, "a DTFT accumulator is not finite (unstable run?)");
+    if (badcot)
+        return fail(m, EMM_ERR_NONFINITE, g_obs ? "the misfit is not finite (a G or G_obs of zero or non-finite value)"
+                                                : "g_bar holds a non-finite value");
     chi_acc = g_obs ? chi : 0.0;
 
     // ---- adjoint set-up ----

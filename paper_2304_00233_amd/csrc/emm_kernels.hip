@@ -51,7 +51,8 @@ __device__ __forceinline__ void st1(float *p, float v) {
 
 // Receiver sample + DTFT: one wavefront per (source, receiver, channel)
 // item.  u = sum over the (2r)^3 tensor-product stencil of w * F, reduced in
-// FP64; then acc[f] += u * exp(i w'_f t_n) for every frequency.
+// FP64; then acc[f] += u * exp(i w'_f t_n) for every frequency (lane l takes
+// frequencies l, l + 64, ...).
 template <int R>
 __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
                         const float *F1, const float *F2, int n, int waves = NT / 64) {
@@ -70,9 +71,10 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
         u += (double)wt * (double)F[(unsigned)((bz + c) * (int)p.plane + (by + b) * p.pitch + bx + a)];
     }
     for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
-    if (lane < p.nf) {
-        const double2 ph = p.phase[(long long)n * p.nf + lane];
-        const long long k = (long long)slot * p.nf + lane;
+    // lane fr updates frequencies fr, fr + 64, ... (any number of them)
+    for (int fr = lane; fr < p.nf; fr += 64) {
+        const double2 ph = p.phase[(long long)n * p.nf + fr];
+        const long long k = (long long)slot * p.nf + fr;
         if (p.dft_mode == 0) {
             double2 a = p.acc[k];
             a.x += u * ph.x;

@@ -172,3 +172,29 @@ def test_host_stability_limit_matches_oracle(emm, rd):
     assert st_hi == -6
     st_lo, _ = _create_status(emm, xs, rs, rd=rd, nb=w.nb, ne=w.ne, dt_override=limit * (1 - 1e-9))
     assert st_lo != -6          # passes validation (then needs a device)
+
+
+def test_create_rejects_grids_beyond_32_bit_offsets(emm):
+    """The kernels address one field array with 32-bit offsets, so a padded
+    grid of 2^31 cells or more (here 1290^3 nodes: (1290 + 34, rounded up to
+    1344) x 1324 x 1324 = 2.36e9 cells) is refused with EMM_ERR_GRID before
+    the resistivity arrays are read (a single value is passed) and before
+    any device call."""
+    lib = emm._lib
+
+    def status(n, rho):
+        xs = [np.arange(k, dtype=np.float64) * 10.0 for k in n]
+        g = emm.emm_grid(n[0], n[1], n[2], *(a.ctypes.data_as(C.POINTER(C.c_double)) for a in xs),
+                         *(a.ctypes.data_as(C.POINTER(C.c_float)) for a in rho))
+        o = emm.emm_default_options()
+        o.dt_override = 1e30          # a valid grid then fails the CFL check, still before the device
+        h = C.c_void_p()
+        return lib.emm_create(C.byref(g), C.byref(o), C.byref(h)), emm.emm_last_error(None)
+
+    one = np.ones(1, np.float32)
+    st, msg = status((1290, 1290, 1290), [one] * 3)
+    assert st == -2 and "2^31" in msg
+    n = (12, 11, 10)
+    full = np.ones((n[2], n[1], n[0]), np.float32)
+    st, _ = status(n, [full] * 3)
+    assert st == -6

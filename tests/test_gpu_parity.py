@@ -256,6 +256,48 @@ def test_multi_model_batch_equals_single_forwards(emm):
     assert rep["ok"], rep
 
 
+def test_more_frequencies_than_lanes(emm):
+    """70 frequencies: lane l of a DTFT wavefront updates frequencies l and
+    l + 64; both accumulator modes against the oracle."""
+    freqs = tuple(np.geomspace(0.2, 5.0, 70))
+    w = configs.small_case(seed=15, shape=(24, 22, 20), nt=300, freqs=freqs, nrec=4)
+    G_o, info_o = F.forward(w)
+    for mode in (0, 1):
+        G_g, _ = _run(emm, w.with_(nt=info_o["nt"], dft_mode=mode))
+        rep = compare(G_g, G_o, w.channels)
+        print(f"[parity] 70 frequencies dft_mode={mode}: {rep}", flush=True)
+        assert rep["ok"], rep
+        assert np.all(np.abs(G_g[..., 64:]) > 0)
+
+
+@pytest.mark.parametrize("comp", [0, 2])
+def test_stretched_whole_space(emm, comp):
+    """The z axis stretched by 1.2 around the source (injection control
+    volume on a non-uniform axis): GPU against the oracle, and the GPU result
+    against the analytic whole-space dipole."""
+    w = configs.stretched_whole_space(comp=comp)
+    G_g, _, _ = _check(emm, w, f"stretched whole space, dipole along axis {comp}")
+    d = [0.0, 0.0, 0.0]
+    d[comp] = 1.0
+    E, _ = A.dipole_fields([0.0, 0.0, 0.0], d, w.receivers, 1.0, 1.0)
+    ratio = G_g[0, :, 0, 0] / E[:, comp]
+    assert np.max(np.abs(np.abs(ratio) - 1.0)) <= 0.03
+    assert np.max(np.abs(np.degrees(np.angle(ratio)))) <= 2.0
+
+
+def test_reciprocity_marine_stretched_z(emm):
+    """Source and receiver swapped between a point in the water and one 500 m
+    into the sediment on the marine z axis with CPML: each run against the
+    oracle, and the GPU pair reciprocal to the oracle's level (5.2e-4)."""
+    w, a, b = configs.marine_reciprocity()
+    G_ab, _, _ = _check(emm, w, "marine reciprocity a -> b")
+    G_ba, _, _ = _check(emm, w.with_(sources=b[None, :], receivers=a[None, :]),
+                        "marine reciprocity b -> a")
+    err = abs(G_ab.ravel()[0] / G_ba.ravel()[0] - 1.0)
+    print(f"[parity] GPU reciprocity on the stretched marine axis: {err:.3e}", flush=True)
+    assert err <= 1e-2
+
+
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="marine oracle result not generated")
 def test_marine_layered_full_size_vs_stored_oracle(emm):
     g = json.load(open(GOLDEN))

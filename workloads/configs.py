@@ -294,3 +294,63 @@ def uniform_cube(n: int, rd: int = 2, nt: int = 100) -> Workload:
     return Workload(f"uniform_cube_{n}", x, x.copy(), x.copy(), r11, r22, r33,
                     sources=np.array([[0.0, 0.0, 0.0]]), receivers=rec,
                     freqs=np.array([1.0]), rd=rd, nb=10, ne=rd + 5, nt=nt)
+
+
+# --------------------------------------------------------------------------
+# Stretched-axis pins of the injection control volume and the padding.
+# --------------------------------------------------------------------------
+def stretched_z_axis(ratio: float = 1.2, d0: float = 20.0, z_fine: float = -600.0,
+                     n_down: int = 22, n_up: int = 20) -> np.ndarray:
+    """z axis whose intervals grow geometrically by `ratio` away from a fine
+    point z_fine (first interval d0 on each side).  Below z_fine every node
+    has an interval below it `ratio` times the one above it, so the dual
+    interval at a node, (h_{k-1} + h_k)/2, differs from the primal one below
+    it by 2 ratio/(1 + ratio) (9 % at 1.2)."""
+    down = grids.axis_from_intervals(z_fine, grids.geometric_intervals(d0, ratio, n_down))
+    up = grids.axis_from_intervals(z_fine, -grids.geometric_intervals(d0, ratio, n_up))
+    return np.concatenate([up[::-1], down[1:]])
+
+
+def stretched_whole_space(comp: int = 0, ratio: float = 1.2, n: int = 60, d: float = 80.0,
+                          nt: int = 0) -> Workload:
+    """Homogeneous 1 ohm-m whole space on a uniform 80 m x, y grid and the
+    strongly stretched z axis of `stretched_z_axis` (the source sits 600 m
+    below the fine point, in cells of ~124 and ~149 m whose neighbours
+    differ by `ratio`); a unit dipole along axis `comp` at the origin, 10
+    receivers on the x axis at 400..2000 m on both sides, 1 Hz."""
+    x = grids.centred_uniform_axis(n, d)
+    z = stretched_z_axis(ratio)
+    r11, r22, r33 = _uniform_rho(n, n, len(z), 1.0)
+    off = np.array([400.0, 800.0, 1200.0, 1600.0, 2000.0])
+    rx = np.concatenate([-off[::-1], off])
+    rec = np.stack([rx, np.zeros_like(rx), np.zeros_like(rx)], axis=1)
+    return Workload(f"stretched_whole_space_q{ratio:g}_c{comp}", x, x.copy(), z, r11, r22, r33,
+                    sources=np.array([[0.0, 0.0, 0.0]]), receivers=rec,
+                    freqs=np.array([1.0]), src_comp=np.array([comp], np.int32),
+                    chan_mask=1 << comp, rd=2, nb=10, ne=7, f0=1.0, nt=nt)
+
+
+def marine_reciprocity(n: int = 40, freq: float = 0.75, extend_z: int = 0) -> tuple:
+    """The marine z axis (25 m at the seafloor, growing by ~1.047 up to the
+    sea surface and by 1.05 down) under a 40 x 40 node, 100 m horizontal
+    grid; 0.3125 ohm-m water over 1 ohm-m sediment; CPML on every face; Ex
+    only.  Returns (workload, a, b): two points with different local
+    stretching (50 m above the seafloor in the water, 500 m below it) for
+    the swap G(b; a) = G(a; b).  extend_z > 0 continues the z axis by that
+    many nodes at each end with the end intervals (a longer box of the same
+    medium)."""
+    x = grids.centred_uniform_axis(n, 100.0)
+    z = marine_z_128x128x96()
+    if extend_z > 0:
+        h0, h1 = z[1] - z[0], z[-1] - z[-2]
+        z = np.concatenate([z[0] - h0 * np.arange(extend_z, 0, -1), z,
+                            z[-1] + h1 * np.arange(1, extend_z + 1)])
+    m = BlockModel(background=1.0)
+    m.add_layer(-np.inf, 1000.0, 0.3125)
+    r11, r22, r33 = _model_arrays(m, x, x, z)
+    a = np.array([-600.0, -150.0, 950.0])
+    b = np.array([700.0, 250.0, 1500.0])
+    w = Workload(f"marine_reciprocity_{n}x{n}x{len(z)}", x, x.copy(), z, r11, r22, r33,
+                 sources=a[None, :], receivers=b[None, :], freqs=np.array([freq]),
+                 chan_mask=1, rd=2, nb=10, ne=7, f0=1.0)
+    return w, a, b
