@@ -1,23 +1,28 @@
 """Benchmark of the FDTD hot path on one MI355X.
 
-A step is one full forward modelling of the marine layered workload
-(128 x 128 x 96 nodes, 162 x 162 x 130 padded cells, 3 frequencies,
-101 receivers x 6 channels, one x-dipole): per-forward set-up, every time
-step (E step with injection and H-channel DTFT, H step with E-channel DTFT)
-and the Green's-function normalisation.  The model is created (and its
-arrays uploaded) before the timed region.
+Default workload: the large marine grid (400 x 400 x 200 nodes, 438 x 438 x
+238 padded cells), 8th order in space, 8 towed x-dipoles in one batched
+launch per half step, 400 seafloor receivers x 6 channels, 5 frequencies
+0.1..2 Hz, FP32 fields with the compensated FP32 DTFT.  A step is one
+emm_forward of the 8 sources over a window of --window time steps (every
+row of the hot path: per-forward set-up, E step with injection and H-channel
+DTFT, H step with E-channel DTFT, Green's-function normalisation); the
+model is created (and its arrays uploaded) before the timed region.
 
-Prints one JSON line: Gcell.step/s (padded cells x time steps / wall time),
-the roofline of the dominant kernel (E step: algorithmic bytes / average
-kernel duration from HIP events recorded around every launch in the timed
-region), and the FP64 oracle timed on the host cores on a bounded sample.
+Prints one JSON line: source-cell updates per second (padded cells x time
+steps x sources / wall time), the roofline of the dominant kernel (the E
+step: algorithmic bytes per launch / its average duration from HIP events
+that the dispatch stamps at kernel start and end, sampled in the timed
+region), the batched forward + gradient against the plain one-source loops,
+the accuracy of the FP32 path against the stored FP64 oracle result of one
+source at the full step count, and the FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import subprocess
 import os
+import subprocess
 import sys
 import time
 
@@ -25,32 +30,77 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of one E-step launch on the marine workload, measured with
-# rocprofv3 --pmc FETCH_SIZE (x 2.0) and --pmc WRITE_SIZE (x 1.0), the factors
-# from a 1 GiB copy kernel: 54 421.1 KiB read and 46 143.4 KiB written (32 x 8
-# tiles, 5 planes per block, compact dt/eps).  Valid for the kernel as
-# profiled; None when the kernel has changed since, until re-measured.
-E_STEP_TRAFFIC_BYTES = (54421.1 * 2.0 + 46143.4 * 1.0) * 1024
-# the same for one launch of the fused step kernel (None until measured)
-LEAP_TRAFFIC_BYTES = None
+LARGE_GOLDEN = os.path.join(ROOT, "tests", "golden", "large_marine_oracle.json")
+MARINE_GOLDEN = os.path.join(ROOT, "tests", "golden", "marine_layered_oracle.json")
+SHALLOW_GOLDEN = os.path.join(ROOT, "tests", "golden", "shallow_marine_air_oracle.json")
+
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE (x 2.0) and WRITE_SIZE
+# (x 1.0), the factors from a 1 GiB copy kernel, keyed by workload, kernel and
+# launch configuration (tile width, rows per wavefront, z planes per block,
+# nontemporal hint, compact dt/eps, sources).  A run whose autotuned launch
+# differs reports null: the counters belong to the kernel as profiled.
+TRAFFIC_KIB = {
+    # (workload, kernel, tx, ry, kz, nontemporal, compact, nsrc): (FETCH_SIZE KiB, WRITE_SIZE KiB)
+    ("marine_layered_128x128x96", "e_step", 32, 1, 5, 0, 1, 1): (54421.1, 46143.4),
+}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, nt_sample: int):
+def host_cores():
+    """Cores this process may use: its CPU affinity, capped by a cgroup CPU
+    quota when one is set; plus the CPU model name."""
+    aff = len(os.sched_getaffinity(0))
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = max(1, int(-(-int(q) // int(per))))
+    except (OSError, ValueError):
+        pass
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": aff, "cgroup_quota_cpus": quota,
+            "usable": min(aff, quota) if quota else aff, "model": model}
+
+
+def cpu_baseline(w, steps_all: int, steps_one: int):
+    """The FP64 oracle (C/OpenMP, one source) on the host: all usable cores
+    over `steps_all` time steps and one thread over `steps_one`."""
     from oracle import forward as F
-    threads = min(16, os.cpu_count() or 1)
-    F.forward(w, threads=threads, nt=2)       # load + warm
-    t = time.perf_counter()
-    F.forward(w, threads=threads, nt=nt_sample)
-    dt = time.perf_counter() - t
-    cells = w.padded_cells
-    return {"value": cells * nt_sample / dt / 1e9, "unit": "Gcell*step/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{w.name}, first {nt_sample} time steps, FP64 C/OpenMP oracle, "
-                      f"{dt:.1f} s wall"}
+    hc = host_cores()
+    w1 = w.with_(sources=w.sources[:1], src_comp=w.src_comp[:1])
+    cells = w1.padded_cells
+    out = {"unit": "Gcell*step/s", "kind": "oracle", "cpu": hc}
+
+    def rate(threads, steps):
+        F.forward(w1, threads=threads, nt=1)          # load, set-up and first touch
+        t = time.perf_counter()
+        F.forward(w1, threads=threads, nt=steps)
+        dt = time.perf_counter() - t
+        t = time.perf_counter()
+        F.forward(w1, threads=threads, nt=1)          # the per-call set-up alone
+        setup = time.perf_counter() - t
+        return cells * (steps - 1) / max(1e-9, dt - setup) / 1e9, dt
+    log(f"[bench] oracle on {hc['usable']} cores, {steps_all} steps")
+    v_all, t_all = rate(hc["usable"], steps_all)
+    log(f"[bench] oracle on 1 core, {steps_one} steps")
+    v_one, t_one = rate(1, steps_one)
+    out.update({"value": v_all, "cores": hc["usable"], "one_thread_value": v_one,
+                "sample": f"{w.name}, one source, FP64 C/OpenMP oracle: {steps_all} time steps on "
+                          f"{hc['usable']} threads ({t_all:.1f} s wall) and {steps_one} steps on 1 "
+                          f"thread ({t_one:.1f} s); rate over the steps after the first, the "
+                          f"per-call set-up subtracted"})
+    return out
 
 
 def stream_reference(reps: int = 20):
@@ -75,51 +125,155 @@ def stream_reference(reps: int = 20):
     return {"kernel": "device copy of 1 GiB (torch copy_)", "GBs": nbytes / sec / 1e9}
 
 
-def batched_comparison(emm, w, nsrc: int, group: int, ckpt: int):
-    """16 towed x-dipoles (500 m spacing, 50 m above the seabed) on the same
-    model: the plain loop of one-source forwards, one batched forward of all
-    sources (sources grouped to stay in the Infinity Cache, and all in one
-    time loop), and batched forward + gradient (log misfit against data from
-    the batched forward scaled by 1.01) in groups of `group` sources that
-    keep checkpoints every `ckpt` steps.  Returns timings and the largest
-    difference between batched and plain results."""
+def kernel_bytes(info, nsrc):
+    """Bytes of one E-step and one H-step launch over nsrc sources:
+    the section-8(d) count (FP32 dt/eps read once: (36 S + 12) N for the E
+    step, 36 S N for the H step, + 16 B per CPML slab cell per axis per
+    source) and the bytes the launch moves (the E step reads 4 B of compact
+    dt/eps per cell instead of 12 when it uses that form)."""
+    N = float(info["cells"])
+    e1 = float(info["e_bytes"])          # one source, as the run moved them
+    ce_one = (4.0 if info["ce_table"] else 12.0) * N
+    per_src_e = e1 - ce_one
+    per_src_h = float(info["h_bytes"])
+    return {"e_8d": nsrc * per_src_e + 12.0 * N, "e_moved": nsrc * per_src_e + ce_one,
+            "h": nsrc * per_src_h}
+
+
+def traffic(workload, kernel, info, nsrc):
+    key = (workload, kernel, info["tile_x"], info.get("tile_rows", 1), info["tile_kz"],
+           info["nontemporal"], info["ce_table"], nsrc)
+    kib = TRAFFIC_KIB.get(key)
+    if kib is None:
+        return None
+    return (kib[0] * FETCH_SCALE + kib[1] * WRITE_SCALE) * 1024.0
+
+
+def timed_forwards(m, steps, warmup, label):
+    for i in range(warmup):
+        m.forward()
+        log(f"[bench] {label} warmup {i} done")
+    acc = dict(e_ms=0.0, h_ms=0.0, e_n=0, h_n=0, dev_ms=0.0)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        m.forward()
+        inf = m.info()
+        acc["e_ms"] += inf["e_kernel_ms"]
+        acc["h_ms"] += inf["h_kernel_ms"]
+        acc["e_n"] += inf["e_launches"]
+        acc["h_n"] += inf["h_launches"]
+        acc["dev_ms"] += inf["forward_ms"]
+    wall = time.perf_counter() - t0
+    log(f"[bench] {label}: {steps} timed steps in {wall:.2f} s")
+    return wall, acc, m.info()
+
+
+def accuracy_vs_golden(emm, gold_path, wl, label, **opt):
+    """One source of the workload at the stored result's full step count,
+    FP64 and compensated-FP32 accumulators, against the FP64 oracle result:
+    per-result amplitude and phase error above the noise floor (max, p99,
+    count below the floor)."""
     import numpy as np
-    from workloads import configs
-    src = configs.towline_sources(nsrc, 500.0, 950.0)
-    comp = np.zeros(nsrc, dtype=np.int32)
-    out = {"sources": nsrc, "gradient_group": group, "checkpoint_every": ckpt}
+    from tests.parity import compare
+    g = json.load(open(gold_path))
+    G_o = (np.array(g["re"]) + 1j * np.array(g["im"])).reshape(g["shape"])
+    s = g.get("source_index", 0)
+    w1 = wl.with_(sources=wl.sources[s:s + 1], src_comp=wl.src_comp[s:s + 1], nt=g["nt"])
+    out = {"oracle": os.path.relpath(gold_path, ROOT), "time_steps": g["nt"], "source_index": s}
+    for mode, name in ((1, "fp32_kahan"), (0, "fp64")):
+        t = time.perf_counter()
+        with emm.Model(w1.with_(dft_mode=mode), tile_kz=-1, graph_steps=64, **opt) as m:
+            G = m.forward()
+        rep = compare(G, G_o, g["channels"])
+        rep["forward_s"] = time.perf_counter() - t
+        out[name] = rep
+        log(f"[bench] {label} accuracy {name}: {rep}")
+    return out
+
+
+def large_batched(emm, w, window, t_batched_fwd):
+    """8 sources on the large grid over `window` steps: the plain loop of
+    one-source forwards, the batched forward (the benchmark step), the
+    batched forward + gradient (of L = 1/2 sum |G|^2, given by its cotangent
+    G: within a window shorter than a converged run the far receivers still
+    read exactly zero, where a log misfit is undefined; sources grouped per
+    sweep by the library's checkpoint plan), and the one-source-at-a-time
+    forward + gradient loop."""
+    import numpy as np
+    nsrc = len(w.sources)
+    out = {"sources": nsrc, "time_steps": window, "batched_forward_s": t_batched_fwd}
     with emm.Model(w, tile_kz=-1, graph_steps=64) as m:
-        m.forward(sources=src[:1], src_comp=comp[:1])           # tune + warm
+        m.forward(sources=w.sources[:1], src_comp=w.src_comp[:1])        # tune for 1 + warm
         t = time.perf_counter()
-        plain = [m.forward(sources=src[i:i + 1], src_comp=comp[i:i + 1]) for i in range(nsrc)]
+        plain = [m.forward(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1])
+                 for s in range(nsrc)]
         out["plain_forward_loop_s"] = time.perf_counter() - t
-        m.forward(sources=src, src_comp=comp)                   # tune for the group + warm
+        log(f"[bench] large: plain forward loop {out['plain_forward_loop_s']:.2f} s")
+        Gb = m.forward()
+        out["batched_equals_plain_bitwise"] = bool(np.array_equal(Gb, np.concatenate(plain, 0)))
+        m.gradient(g_bar=Gb[:1], sources=w.sources[:1], src_comp=w.src_comp[:1])   # warm
         t = time.perf_counter()
-        Gb = m.forward(sources=src, src_comp=comp)
-        out["batched_forward_s"] = time.perf_counter() - t
-        out["batched_sources_per_time_loop"] = m.info()["src_group"]
-    # all sources in one time loop (every launch updates all of them)
-    with emm.Model(w, tile_kz=-1, graph_steps=64, src_group=-1) as m:
-        m.forward(sources=src, src_comp=comp)                   # tune for nsrc + warm
+        for s in range(nsrc):
+            m.gradient(g_bar=Gb[s:s + 1], sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1])
+        out["plain_forward_gradient_loop_s"] = time.perf_counter() - t
+        log(f"[bench] large: one-source forward + gradient loop {out['plain_forward_gradient_loop_s']:.2f} s")
         t = time.perf_counter()
-        G1 = m.forward(sources=src, src_comp=comp)
-        out["one_loop_forward_s"] = time.perf_counter() - t
-    Gp = np.concatenate(plain, axis=0)
-    out["max_abs_diff_batched_vs_plain"] = float(max(np.max(np.abs(Gb - Gp)), np.max(np.abs(G1 - Gp))))
-    G_obs = Gb * 1.01
-    with emm.Model(w, tile_kz=-1, checkpoint_every=ckpt, graph_steps=64) as m:
-        m.forward(sources=src[:group], src_comp=comp[:group])   # tune + warm
-        t = time.perf_counter()
-        for g0 in range(0, nsrc, group):
-            sl = slice(g0, min(nsrc, g0 + group))
-            m.forward(sources=src[sl], src_comp=comp[sl])
-            m.gradient(g_obs=G_obs[sl], sources=src[sl], src_comp=comp[sl])
+        m.gradient(g_bar=Gb)
         out["batched_forward_gradient_s"] = time.perf_counter() - t
-    out["speedup_batched_forward_vs_plain_loop"] = out["plain_forward_loop_s"] / out["batched_forward_s"]
-    out["speedup_one_loop_vs_plain_loop"] = out["plain_forward_loop_s"] / out["one_loop_forward_s"]
+        i = m.info()
+        out["gradient_sources_per_sweep"] = i["src_group"]
+        out["checkpoint_outer_inner"] = [i["ckpt_outer"], i["ckpt_inner"]]
+        out["checkpoint_GiB"] = i["ckpt_bytes"] / 2 ** 30
+        log(f"[bench] large: batched forward + gradient {out['batched_forward_gradient_s']:.2f} s")
+    out["batched_forward_speedup_vs_plain_forward_loop"] = out["plain_forward_loop_s"] / t_batched_fwd
     out["batched_fwd_grad_over_plain_forward_loop"] = (out["batched_forward_gradient_s"] /
                                                        out["plain_forward_loop_s"])
+    out["batched_fwd_grad_speedup_vs_plain_fwd_grad_loop"] = (out["plain_forward_gradient_loop_s"] /
+                                                             out["batched_forward_gradient_s"])
     return out
+
+
+def small_towline(emm, nsrc: int = 16):
+    """16 x-dipoles every 250 m along x on the 48^3 plain-forward model, all
+    in one batched launch per half step, against the plain loop of
+    one-source forwards (a launch-bound grid: 82^3 padded cells)."""
+    import numpy as np
+    from workloads import configs
+    w = configs.towline_small(nsrc)
+    out = {"workload": w.name, "sources": nsrc}
+    with emm.Model(w, tile_kz=-1, graph_steps=64, src_group=-1) as m:
+        m.forward(sources=w.sources[:1], src_comp=w.src_comp[:1])
+        m.forward()
+        t = time.perf_counter()
+        plain = [m.forward(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1]) for s in range(nsrc)]
+        out["plain_forward_loop_s"] = time.perf_counter() - t
+        t = time.perf_counter()
+        Gb = m.forward()
+        out["batched_forward_s"] = time.perf_counter() - t
+        out["time_steps"] = m.info()["nt"]
+    out["bitwise_equal"] = bool(np.array_equal(Gb, np.concatenate(plain, 0)))
+    out["speedup"] = out["plain_forward_loop_s"] / out["batched_forward_s"]
+    return out
+
+
+def marine_leg(emm, steps: int):
+    """The 128 x 128 x 96 marine layered workload (162 x 162 x 130 padded
+    cells, one source, full step count): its working set (~150 MB) sits in
+    the 256 MB Infinity Cache, so its bandwidth is an effective (cache-fed)
+    figure, not an HBM one."""
+    from workloads import configs
+    nt = json.load(open(MARINE_GOLDEN))["nt"] if os.path.exists(MARINE_GOLDEN) else 0
+    w = configs.marine_layered(nt=nt)
+    with emm.Model(w, profile=1, graph_steps=64, tile_kz=-1) as m:
+        wall, acc, info = timed_forwards(m, steps, 1, "marine")
+    e_us = acc["e_ms"] / max(1, acc["e_n"]) * 1e3
+    return {"workload": w.name, "cache_resident": True, "time_steps": info["nt"],
+            "gcell_step_per_s": info["cells"] * info["nt"] * steps / wall / 1e9,
+            "ms_per_forward": wall / steps * 1e3, "e_step_us": e_us,
+            "e_step_effective_GBs": info["e_bytes"] / e_us / 1e3,
+            "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"],
+                       "tile_rows": info["tile_rows"], "nontemporal": info["nontemporal"],
+                       "compact_dt_eps": info["ce_table"]}}
 
 
 def multi_model_comparison(emm, graph: int):
@@ -181,82 +335,35 @@ def multi_model_comparison(emm, graph: int):
             "batch_gcell_step_per_s": cellsteps / t_bat / 1e9, "bitwise_equal": same}
 
 
-def large_fwd_grad(emm, nt: int, group: int, graph: int):
-    """The 400 x 400 x 200 marine grid at 8th order (438 x 438 x 238 padded
-    cells), 8 x-dipoles, 400 receivers, 5 frequencies, compensated FP32 DTFT:
-    plain loop of one-source forwards, one batched forward of the 8
-    sources, and forward + gradient (log misfit against the batched result
-    scaled by 1.01) in groups of `group` sources, each under the planned
-    checkpoint schedule."""
-    from workloads import configs
-    w = configs.large_marine(nt=nt, rd=4, nsrc=8)
-    out = {"workload": w.name, "time_steps": nt, "sources": 8, "gradient_group": group}
-    with emm.Model(w, tile_kz=-1, graph_steps=graph) as m:
-        m.forward(sources=w.sources[:1], src_comp=w.src_comp[:1])         # tune + warm
-        t = time.perf_counter()
-        for s in range(8):
-            m.forward(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1])
-            log(f"[bench] large: plain forward of source {s} done")
-        out["plain_forward_loop_s"] = time.perf_counter() - t
-        m.forward()                                                     # tune for 8 + warm
-        log("[bench] large: batched warm-up done")
-        t = time.perf_counter()
-        Gb = m.forward()
-        out["batched_forward_s"] = time.perf_counter() - t
-        log("[bench] large: batched forward done")
-        G_obs = Gb * 1.01
-        sched = []
-        t = time.perf_counter()
-        for g0 in range(0, 8, group):
-            sl = slice(g0, min(8, g0 + group))
-            m.gradient(g_obs=G_obs[sl], sources=w.sources[sl], src_comp=w.src_comp[sl])
-            i = m.info()
-            sched.append([i["ckpt_outer"], i["ckpt_inner"], i["ckpt_bytes"] / 2 ** 30, i["src_group"]])
-            log(f"[bench] large: gradient of sources {g0}..{sl.stop - 1} done, schedule {sched[-1]}")
-        out["forward_gradient_s"] = time.perf_counter() - t
-        out["checkpoint_schedule_outer_inner_GiB_sources_per_sweep"] = sched
-        out["cells"] = m.info()["cells"]
-    out["batched_forward_vs_plain_loop"] = out["plain_forward_loop_s"] / out["batched_forward_s"]
-    out["forward_gradient_over_plain_forward_loop"] = out["forward_gradient_s"] / out["plain_forward_loop_s"]
-    return out
-
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2000)
-    ap.add_argument("--workload", default="marine", choices=["marine", "large", "cube", "shallow"],
-                    help="marine: the headline 128x128x96 workload; large: the 400x400x200 "
-                         "marine grid (one source); cube: uniform n^3 (--cube-n); shallow: "
-                         "128x128x80 shallow water with the air boundary")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="large", choices=["large", "marine", "cube", "shallow"],
+                    help="large: the 400x400x200 grid at 8th order with 8 batched sources (the "
+                         "headline); marine: 128x128x96, one source, full step count; cube: "
+                         "uniform n^3 (--cube-n); shallow: 128x128x80 with the air boundary")
+    ap.add_argument("--window", type=int, default=256,
+                    help="time steps per forward (one benchmark step) of the large workload")
+    ap.add_argument("--sources", type=int, default=8, help="sources of the large workload")
     ap.add_argument("--cube-n", type=int, default=400)
     ap.add_argument("--rd", type=int, default=0, help="override the stencil half length")
-    ap.add_argument("--nt", type=int, default=0, help="override the time-step count")
+    ap.add_argument("--nt", type=int, default=0, help="override the time-step count (not large)")
     ap.add_argument("--graph", type=int, default=64, help="time steps per captured hipGraph (0: direct launches)")
-    ap.add_argument("--fused", type=int, default=0, choices=[0, 1],
-                    help="1: one fused launch per time step (E and H updates)")
+    ap.add_argument("--fused", type=int, default=0, choices=[0, 1])
     ap.add_argument("--tile-kz", type=int, default=-1, help="z planes per block (-1: autotuned)")
-    ap.add_argument("--tile-x", type=int, default=0, choices=(0, 32, 64),
-                    help="columns per block of the stencil kernels (0: autotuned or by the grid)")
-    ap.add_argument("--batched", type=int, default=16,
-                    help="sources of the batched comparison (0: skip)")
-    ap.add_argument("--grad-group", type=int, default=8)
-    ap.add_argument("--grad-ckpt", type=int, default=128)
-    ap.add_argument("--no-multi-model", action="store_true",
-                    help="skip timing 8 models of uneven sizes in one hipGraph vs one after another")
-    ap.add_argument("--large-fwd-grad", type=int, default=0, metavar="NT",
-                    help="also time the 8-source 8th-order forward + gradient on the 400x400x200 "
-                         "grid with NT time steps (0: skip)")
-    ap.add_argument("--large-group", type=int, default=8,
-                    help="sources per emm_gradient call of --large-fwd-grad (the library then "
-                         "groups them per sweep by its checkpoint plan)")
-    ap.add_argument("--gradient-sample", type=int, default=0, metavar="NT",
-                    help="only run one forward + gradient of the marine (or, with --workload "
-                         "large, the large-grid) workload cut to NT steps (for kernel traces of "
-                         "the adjoint) and exit")
+    ap.add_argument("--tile-x", type=int, default=0, choices=(0, 32, 64))
+    ap.add_argument("--tile-rows", type=int, default=0, choices=(0, 1, 2, 4))
+    ap.add_argument("--quick", action="store_true",
+                    help="only the timed steps (no batched, accuracy, marine, towline legs)")
+    ap.add_argument("--multi-model", action="store_true",
+                    help="also time 8 models of uneven sizes side by side (emm_forward_batch) "
+                         "against one after another")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=50, help="oracle steps on all cores")
+    ap.add_argument("--cpu-steps-one", type=int, default=6, help="oracle steps on one core")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     ap.add_argument("--stream-reference", action="store_true",
@@ -274,30 +381,14 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copied {a.numel() * 4} bytes")
         return
-    if args.gradient_sample:
-        from paper_2304_00233_amd import emm
-        from workloads import configs
-        if args.workload == "large":
-            w = configs.large_marine(nt=args.gradient_sample, rd=args.rd or 4, nsrc=1)
-        else:
-            w = configs.marine_layered(nt=args.gradient_sample)
-        with emm.Model(w, tile_kz=-1, graph_steps=64) as m:
-            G = m.forward()
-            t = time.perf_counter()
-            m.gradient(g_obs=G * 1.01)
-            dt = time.perf_counter() - t
-            i = m.info()
-        log(f"[bench] gradient sample: {w.name}, {args.gradient_sample} steps, forward + gradient "
-            f"{dt * 1e3:.1f} ms, checkpoints every {i['ckpt_outer']} (inner {i['ckpt_inner']})")
-        return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by "
-              "source with no communication between GPUs", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): nothing in this build "
+              "runs on a second GPU; the path would shard by source with no communication "
+              "between GPUs", file=sys.stderr)
         sys.exit(2)
 
     # the streaming reference runs in a child process before this one touches
-    # the GPU (torch brings its own HIP runtime, which cannot share a process
-    # with the library's)
+    # the GPU (torch loads its own HIP runtime)
     stream_ref = None
     try:
         log("[bench] stream reference (1 GiB device copy, child process)")
@@ -311,112 +402,104 @@ def main():
     from paper_2304_00233_amd import emm
     from workloads import configs
 
-    if args.workload == "marine":
-        w = configs.marine_layered()
-        nt = 0
-        gold = os.path.join(ROOT, "tests", "golden", "marine_layered_oracle.json")
-        if os.path.exists(gold):
-            nt = json.load(open(gold))["nt"]
-        w = w.with_(nt=nt)
+    large = args.workload == "large"
+    if large:
+        rd = args.rd or 4
+        w = configs.large_marine(nt=args.window, rd=rd, nsrc=args.sources)
+        if rd != 4:
+            w = w.with_(ne=rd + 5)
+    elif args.workload == "marine":
+        nt = json.load(open(MARINE_GOLDEN))["nt"] if os.path.exists(MARINE_GOLDEN) else 0
+        w = configs.marine_layered(nt=nt)
     elif args.workload == "shallow":
         w = configs.shallow_marine()
-        gold = os.path.join(ROOT, "tests", "golden", "shallow_marine_air_oracle.json")
-        if os.path.exists(gold):
-            w = w.with_(nt=json.load(open(gold))["nt"])
-    elif args.workload == "large":
-        w = configs.large_marine(nsrc=1).with_(dft_mode=0)
+        if os.path.exists(SHALLOW_GOLDEN):
+            w = w.with_(nt=json.load(open(SHALLOW_GOLDEN))["nt"])
     else:
         w = configs.uniform_cube(args.cube_n)
-    if args.rd:
+    if args.rd and not large:
         w = w.with_(rd=args.rd, ne=args.rd + 5)
-    if args.nt:
+    if args.nt and not large:
         w = w.with_(nt=args.nt)
-    log(f"[bench] workload {w.name} padded cells {w.padded_cells}")
+    nsrc = len(w.sources)
+    log(f"[bench] workload {w.name} padded cells {w.padded_cells} sources {nsrc}")
 
     model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz, fused=args.fused,
-                      tile_x=args.tile_x)
-    for i in range(args.warmup):
-        model.forward()
-        log(f"[bench] warmup {i} done")
-    e_ms = h_ms = 0.0
-    e_n = h_n = 0
-    dev_ms = 0.0
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        model.forward()
-        inf = model.info()
-        e_ms += inf["e_kernel_ms"]
-        h_ms += inf["h_kernel_ms"]
-        e_n += inf["e_launches"]
-        h_n += inf["h_launches"]
-        dev_ms += inf["forward_ms"]
-    wall = time.perf_counter() - t0
-    info = model.info()
+                      tile_x=args.tile_x, tile_rows=args.tile_rows)
+    wall, acc, info = timed_forwards(model, args.steps, args.warmup, "main")
     model.close()
     nt = info["nt"]
     cells = info["cells"]
     ms_per_step = wall / args.steps * 1e3
-    value = cells * nt * args.steps / wall / 1e9
-    e_avg_s = e_ms / e_n / 1e3 if e_n else float("nan")
-    h_avg_s = h_ms / h_n / 1e3 if h_n else float("nan")
+    value = cells * nt * nsrc * args.steps / wall / 1e9
+    e_avg_s = acc["e_ms"] / acc["e_n"] / 1e3 if acc["e_n"] else float("nan")
+    h_avg_s = acc["h_ms"] / acc["h_n"] / 1e3 if acc["h_n"] else float("nan")
     fused = bool(info["fused"])
-    kbytes = info["leap_bytes"] if fused else info["e_bytes"]
-    achieved = kbytes / e_avg_s / 1e9
-    log(f"[bench] nt={nt} wall/forward={ms_per_step:.1f} ms device loop/forward="
-        f"{dev_ms / args.steps:.1f} ms e_step avg={e_avg_s * 1e6:.2f} us "
+    kb = kernel_bytes(info, nsrc)
+    if fused:
+        e_bytes = e_moved = info["leap_bytes"] * nsrc
+    else:
+        e_bytes, e_moved = kb["e_8d"], kb["e_moved"]
+    achieved = e_bytes / e_avg_s / 1e9
+    log(f"[bench] nt={nt} wall/step={ms_per_step:.1f} ms device loop/step="
+        f"{acc['dev_ms'] / args.steps:.1f} ms e_step avg={e_avg_s * 1e6:.2f} us "
         f"h_step avg={h_avg_s * 1e6:.2f} us tile_kz={info['tile_kz']} tile_x={info['tile_x']} "
-        f"nontemporal={info['nontemporal']} ce_table={info['ce_table']}")
+        f"tile_rows={info['tile_rows']} nontemporal={info['nontemporal']} ce_table={info['ce_table']}")
+    step_desc = (f"one forward of the {nsrc} sources batched, over a window of {nt} time steps "
+                 f"(of the {18800} of a converged run)" if large else
+                 "one full forward modelling (nt time steps)")
     out = {
-        "metric": "FDTD cell-updates/s (Gcell*step/s) + % HBM peak",
+        "metric": "FDTD cell-updates/s (Gcell*step/s) + % HBM peak; batched fwd+grad vs plain fwd",
         "value": value, "unit": "Gcell*step/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (fields), f64 (DFT)",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (fields), " + ("f32 Kahan-compensated" if w.dft_mode else "f64") + " (DTFT)",
         "data": "synthetic",
-        "config": {"workload": w.name, "padded_cells": cells, "time_steps": nt,
-                   "rd": w.rd, "sources": len(w.sources), "receivers": len(w.receivers),
-                   "channels": 6, "freqs": [float(f) for f in w.freqs],
-                   "step": "one full forward modelling (nt time steps)"},
+        "config": {"workload": w.name, "padded_cells": cells, "time_steps": nt, "rd": w.rd,
+                   "sources": nsrc, "receivers": len(w.receivers), "channels": 6,
+                   "freqs": [float(f) for f in w.freqs], "step": step_desc,
+                   "value_counts": "padded cells x time steps x sources"},
         "roofline": {"bound": "hbm",
-                     "kernel": ("leap (E update + H update of one step, E on the halo recomputed, "
-                                "J, CPML, DTFT)") if fused else
-                               "e_step (curl H + CPML + J + E update + H DTFT)",
+                     "kernel": ("leap (E update + H update of one step)") if fused else
+                               "e_step (curl H + CPML + J + E update + H-channel DTFT)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (LEAP_TRAFFIC_BYTES if fused else E_STEP_TRAFFIC_BYTES)
-                     if args.workload == "marine" else None,
-                     "bytes_per_launch": kbytes, "avg_launch_us": e_avg_s * 1e6},
-        "device_loop_ms_per_step": dev_ms / args.steps,
-        # the same run counted over the model's interior nodes only (the
-        # padding of nb + ne cells per face is streamed too, so `value`
-        # counts it)
-        "interior_gcell_step_per_s": (len(w.x1) * len(w.x2) * len(w.x3)) * nt * args.steps / wall / 1e9,
-        "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"],
+                     "traffic": None if fused else traffic(w.name, "e_step", info, nsrc),
+                     "bytes_per_launch": e_bytes, "bytes_moved_per_launch": e_moved,
+                     "moved_GBs": e_moved / e_avg_s / 1e9, "avg_launch_us": e_avg_s * 1e6,
+                     "launches_timed": acc["e_n"]},
+        "interior_gcell_step_per_s": (len(w.x1) * len(w.x2) * len(w.x3)) * nt * nsrc * args.steps / wall / 1e9,
+        "device_loop_ms_per_step": acc["dev_ms"] / args.steps,
+        "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"], "tile_rows": info["tile_rows"],
                    "nontemporal": info["nontemporal"], "compact_dt_eps": info["ce_table"],
                    "graph_steps": args.graph},
-        "fused_step": fused,
     }
     if not fused:
-        out["h_step"] = {"bytes_per_launch": info["h_bytes"], "avg_launch_us": h_avg_s * 1e6,
-                         "achieved_GBs": info["h_bytes"] / h_avg_s / 1e9}
+        out["h_step"] = {"bytes_per_launch": kb["h"], "avg_launch_us": h_avg_s * 1e6,
+                         "achieved_GBs": kb["h"] / h_avg_s / 1e9,
+                         "frac": kb["h"] / h_avg_s / 1e9 / HBM_PEAK_GBS,
+                         "traffic": traffic(w.name, "h_step", info, nsrc)}
     if stream_ref:
         out["stream_reference"] = dict(stream_ref)
         out["stream_reference"]["e_step_frac_of_it"] = achieved / stream_ref["GBs"]
-    if args.batched and args.workload == "marine":
-        log(f"[bench] batched comparison with {args.batched} sources")
-        out["batched"] = batched_comparison(emm, w, args.batched, args.grad_group, args.grad_ckpt)
-        log(f"[bench] batched: {out['batched']}")
-    if not args.no_multi_model and args.workload == "marine":
+    if large and not args.quick:
+        log("[bench] batched forward + gradient legs")
+        out["batched"] = large_batched(emm, w, nt, ms_per_step / 1e3)
+        if os.path.exists(LARGE_GOLDEN):
+            log("[bench] accuracy against the stored FP64 oracle result (full step count)")
+            out["accuracy"] = accuracy_vs_golden(emm, LARGE_GOLDEN, configs.large_marine(rd=4, nsrc=8),
+                                                 "large")
+        log("[bench] towline of 16 sources on the 48^3 model")
+        out["towline_48cube"] = small_towline(emm)
+        log("[bench] marine (cache-resident) leg")
+        out["marine"] = marine_leg(emm, 3)
+    if args.multi_model:
         log("[bench] multi-model comparison")
         out["multi_model"] = multi_model_comparison(emm, args.graph or 64)
-        log(f"[bench] multi-model: {out['multi_model']}")
-    if args.large_fwd_grad:
-        log(f"[bench] large 8-source forward + gradient, {args.large_fwd_grad} steps")
-        out["large_fwd_grad"] = large_fwd_grad(emm, args.large_fwd_grad, args.large_group,
-                                               args.graph or 64)
-        log(f"[bench] large: {out['large_fwd_grad']}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps if large else 200,
+                                           args.cpu_steps_one if large else 20)
     print(json.dumps(out), flush=True)
 
 

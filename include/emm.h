@@ -130,6 +130,11 @@ typedef struct {
     int    tile_x;         /* columns per block of the stencil kernels: 64 (x 4 rows) or 32 (x 8
                               rows); 0 = autotuned with tile_kz = -1, else 32 where it leaves
                               fewer idle lanes in the last x tile of a row or at rd >= 3 [0] */
+    int    tile_rows;      /* grid rows each wavefront of a stencil block updates: 1, or 2 / 4
+                              (64-wide tiles of 8 / 16 rows, register-blocked: less staged halo
+                              per cell, more loads per thread, but 2-3 waves per SIMD; needs
+                              tile_x 0 or 64); 0 = 1, and the autotuner (tile_kz = -1) then
+                              tries only the one-row shapes.  Every shape gives the same bits [0] */
 } emm_options;
 
 /* A point electric dipole (the acquisition of Section 5): position in
@@ -166,6 +171,7 @@ typedef struct {
     int    src_group;        /* sources per time loop of the last emm_forward (jobs per graph
                                 after emm_forward_batch) */
     int    tile_x;           /* columns per block of the last forward's stencil kernels */
+    int    tile_rows;        /* grid rows per wavefront of the last forward's stencil kernels */
 } emm_info;
 
 /* Fill *o with the defaults above: the paper's values where it states them

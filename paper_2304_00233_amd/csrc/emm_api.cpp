@@ -66,6 +66,7 @@ struct Tune {
     int stream = 0;    // nontemporal hints
     int compact = 0;   // compact dt/eps in the E step
     int tx = 64;       // tile width of the step kernels
+    int ry = 1;        // rows per wavefront (2, 4: register-blocked 64-wide tiles)
 };
 
 struct emm_model {
@@ -230,10 +231,24 @@ int choose_tx(const emm_model *m, int nsrc) {
     return (m->r >= 3 || e32 > e64 + 0.02) ? 32 : 64;
 }
 
-// x and y tiles over the update set i, j in [r, n - 1 - r] (x tiles start at 0)
-void set_tiles(emm::StepParams &P, const emm_model *m, int tx) {
-    const int rows = emm::kStepThreads / tx;
+// Rows per wavefront of the step kernels: the option, the autotuner's
+// choice, else 1 (one row per wavefront, step_kernel).
+int choose_ry(const emm_model *m, int nsrc) {
+    if (m->opt.tile_rows > 0) return m->opt.tile_rows;
+    if (m->opt.tile_kz < 0) {
+        auto it = m->tuned.find(nsrc);
+        if (it != m->tuned.end()) return it->second.ry;
+    }
+    return 1;
+}
+
+// x and y tiles over the update set i, j in [r, n - 1 - r] (x tiles start at 0);
+// ry > 1: 64-wide tiles of 4 ry rows (register-blocked kernels)
+void set_tiles(emm::StepParams &P, const emm_model *m, int tx, int ry = 1) {
+    if (ry > 1) tx = 64;
+    const int rows = ry > 1 ? (emm::kStepThreads / 64) * ry : emm::kStepThreads / tx;
     P.tx = tx;
+    P.ry = ry > 1 ? ry : 1;
     P.xt = (m->np[0] - m->r + tx - 1) / tx;
     P.yt = (m->np[1] - 2 * m->r + rows - 1) / rows;
 }
@@ -242,6 +257,7 @@ void set_tiles(emm::StepParams &P, const emm_model *m, int tx) {
 void note_run(emm_model *m, const emm::StepParams &Pe) {
     m->info.tile_kz = Pe.kz;
     m->info.tile_x = Pe.tx;
+    m->info.tile_rows = Pe.ry;
     m->info.nontemporal = Pe.stream;
     m->info.ce_table = Pe.cei != nullptr;
     step_bytes(m, m->info.e_bytes, m->info.h_bytes, Pe.cei != nullptr);
@@ -279,6 +295,7 @@ emm_status emm_default_options(emm_options *o) {
     o->ce_table = -1;
     o->src_group = 0;
     o->tile_x = 0;
+    o->tile_rows = 0;
     return EMM_OK;
 }
 
@@ -341,6 +358,8 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
         opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
         opt.airwave < 0 || opt.airwave > 1 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
         opt.fused < 0 || opt.fused > 1 || opt.ce_table < -1 || opt.ce_table > 1 || opt.src_group < -1 || (opt.tile_x != 0 && opt.tile_x != 32 && opt.tile_x != 64) ||
+        (opt.tile_rows != 0 && opt.tile_rows != 1 && opt.tile_rows != 2 && opt.tile_rows != 4) ||
+        (opt.tile_rows > 1 && opt.tile_x == 32) ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -843,7 +862,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.plane = plane;
     P.fstride = fstride;
     P.nb = nb;
-    set_tiles(P, m, choose_tx(m, nsrc));
+    set_tiles(P, m, choose_tx(m, nsrc), choose_ry(m, nsrc));
     P.kz = choose_kz(m, P.xt, P.yt, nsrc);
     P.zc = (z_planes(m) + P.kz - 1) / P.kz;
     P.kmin = kmin_of(m);
@@ -1059,10 +1078,23 @@ emm_status zero_state(emm_model *m, hipStream_t stream) {
     const long long fstride = A.Pe.fstride;
     const size_t acc_elem = m->opt.dft_mode ? sizeof(float4) : sizeof(double2);
     const int nslot = A.nslot + A.ncorner;
-    HIP_OK(m, hipMemsetAsync(m->fields.p, 0, (size_t)6 * A.nsrc * fstride * sizeof(float), stream));
+    const size_t fbytes = (size_t)6 * A.nsrc * fstride * sizeof(float);
     const size_t psi_bytes = (state_floats(m) - 6 * fstride) * A.nsrc * sizeof(float);
+    const size_t abytes = (size_t)nslot * A.nf * acc_elem;
+    HIP_OK(m, hipMemsetAsync(m->fields.p, 0, fbytes, stream));
     if (psi_bytes) HIP_OK(m, hipMemsetAsync(m->psi.p, 0, psi_bytes, stream));
-    HIP_OK(m, hipMemsetAsync(m->acc.p, 0, (size_t)nslot * A.nf * acc_elem, stream));
+    HIP_OK(m, hipMemsetAsync(m->acc.p, 0, abytes, stream));
+    return EMM_OK;
+}
+
+// Events of the profiling path, created once and kept with the model: grow
+// the set to `count`.
+emm_status ensure_events(emm_model *m, size_t count) {
+    while (m->ring.size() < count) {
+        hipEvent_t e = nullptr;
+        HIP_OK(m, hipEventCreate(&e));
+        m->ring.push_back(e);
+    }
     return EMM_OK;
 }
 
@@ -1085,10 +1117,14 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     // directly instead -- the same kernels with the absolute step index --
     // and sampled, so the timing is taken inside the timed loop.
     const bool prof = m->opt.profile != 0;
-    const int sample = 16, ring_pairs = 64;
-    if (prof && m->ring.empty()) {
-        m->ring.assign(4 * ring_pairs, nullptr);
-        for (hipEvent_t &e : m->ring) HIP_OK(m, hipEventCreate(&e));
+    const int sample = 16;
+    if (prof) {
+        // every timed E/H pair of this forward gets its own four events: no
+        // event is recorded twice before the end of the loop reads it
+        const int Kg = m->opt.graph_steps;
+        const long long blocks = Kg > 0 ? (nt / Kg + 7) / 8 : 0;
+        const long long timed_max = blocks * ((Kg + 3) / 4) + (nt + sample - 1) / sample + 1;
+        if ((st = ensure_events(m, (size_t)(4 * timed_max))) != EMM_OK) return st;
     }
     if (!m->ev_loop[0]) {
         HIP_OK(m, hipEventCreate(&m->ev_loop[0]));
@@ -1111,12 +1147,8 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     auto step = [&](int n, bool timed) -> emm_status {
         int slot = -1;
         if (timed) {
-            slot = nslots_used % ring_pairs;
-            if (nslots_used >= ring_pairs) {
-                emm_status s2 = harvest(slot);
-                if (s2 != EMM_OK) return s2;
-            }
-            ++nslots_used;
+            slot = nslots_used++;
+            if ((size_t)(4 * slot + 3) >= m->ring.size()) return fail(m, EMM_ERR_ARG, "profiling events exhausted");
         }
         // timed launches carry their events in the dispatch itself (kernel
         // start and end, as a kernel trace reports them)
@@ -1236,8 +1268,8 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
     HIP_OK(m, hipGetLastError());
     HIP_OK(m, hipEventRecord(m->ev_loop[1], stream));
     if (prof)
-        for (int u = std::max(0, nslots_used - ring_pairs); u < nslots_used; ++u)
-            if ((st = harvest(u % ring_pairs)) != EMM_OK) return st;
+        for (int u = 0; u < nslots_used; ++u)
+            if ((st = harvest(u)) != EMM_OK) return st;
     HIP_OK(m, hipStreamSynchronize(stream));
     float loop_ms = 0.f;
     HIP_OK(m, hipEventElapsedTime(&loop_ms, m->ev_loop[0], m->ev_loop[1]));
@@ -1355,9 +1387,12 @@ emm_status leap_loop(emm_model *m, hipStream_t stream) {
         xp[par].qz1 = at(wr_, A.Pe.psz1);
     }
     const bool prof = m->opt.profile != 0;
-    if (prof && m->ring.empty()) {
-        m->ring.assign(4 * 64, nullptr);
-        for (hipEvent_t &e : m->ring) HIP_OK(m, hipEventCreate(&e));
+    if (prof) {
+        // one event pair per timed launch of this forward (none recorded twice)
+        const int Kg = m->opt.graph_steps;
+        const long long blocks = Kg > 0 ? (nt / Kg + 7) / 8 : 0;
+        const long long timed_max = blocks * ((Kg + 3) / 4) + (nt + 15) / 16 + 1;
+        if ((st = ensure_events(m, (size_t)(2 * timed_max))) != EMM_OK) return st;
     }
     if (!m->ev_loop[0]) {
         HIP_OK(m, hipEventCreate(&m->ev_loop[0]));
@@ -1377,12 +1412,8 @@ emm_status leap_loop(emm_model *m, hipStream_t stream) {
     auto step = [&](int n, bool timed) -> emm_status {
         hipEvent_t t0 = nullptr, t1 = nullptr;
         if (timed) {
-            const int slot = used % 128;
-            if (used >= 128) {
-                emm_status s2 = harvest(slot);
-                if (s2 != EMM_OK) return s2;
-            }
-            ++used;
+            const int slot = used++;
+            if ((size_t)(2 * slot + 1) >= m->ring.size()) return fail(m, EMM_ERR_ARG, "profiling events exhausted");
             t0 = m->ring[2 * slot];
             t1 = m->ring[2 * slot + 1];
         }
@@ -1430,8 +1461,8 @@ emm_status leap_loop(emm_model *m, hipStream_t stream) {
     HIP_OK(m, hipGetLastError());
     HIP_OK(m, hipEventRecord(m->ev_loop[1], stream));
     if (prof)
-        for (int u = std::max(0, used - 128); u < used; ++u)
-            if ((st = harvest(u % 128)) != EMM_OK) return st;
+        for (int u = 0; u < used; ++u)
+            if ((st = harvest(u)) != EMM_OK) return st;
     HIP_OK(m, hipStreamSynchronize(stream));
     float loop_ms = 0.f;
     HIP_OK(m, hipEventElapsedTime(&loop_ms, m->ev_loop[0], m->ev_loop[1]));
@@ -1580,9 +1611,21 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
         if (kz <= 64 && (cand.empty() || cand.back() != kz)) cand.push_back(kz);
     }
     if (std::find(cand.begin(), cand.end(), A.Pe.kz) == cand.end()) cand.push_back(A.Pe.kz);
-    std::vector<int> hints = {0, 1}, compacts = {0}, widths = {64, 32};
+    std::vector<int> hints = {0, 1}, compacts = {0};
+    // tile shapes (width, rows per wavefront): 64 x 4 and 32 x 8; the
+    // register-blocked 64 x 8 and 64 x 16 only when tile_rows asks for them
+    // (measured slower on every grid here: 2-3 waves per SIMD instead of 4-6)
+    std::vector<std::pair<int, int>> shapes = {{64, 1}, {32, 1}};
     if (m->opt.nontemporal >= 0) hints = {m->opt.nontemporal};
-    if (m->opt.tile_x > 0) widths = {m->opt.tile_x};
+    if (m->opt.tile_x > 0 || m->opt.tile_rows > 0) {
+        std::vector<std::pair<int, int>> keep;
+        for (auto sh : {std::make_pair(64, 1), std::make_pair(32, 1), std::make_pair(64, 2),
+                        std::make_pair(64, 4)})
+            if ((m->opt.tile_x == 0 || sh.first == m->opt.tile_x) &&
+                (m->opt.tile_rows == 0 || sh.second == m->opt.tile_rows))
+                keep.push_back(sh);
+        shapes = keep;
+    }
     if (m->cei && m->opt.ce_table == -1) compacts = {0, 1};
     else if (m->cei && m->opt.ce_table == 1) compacts = {1};
     hipEvent_t e0, e1;
@@ -1590,8 +1633,8 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     HIP_OK(m, hipEventCreate(&e1));
     auto time_it = [&](const Tune &c, int steps, float &ms) -> emm_status {
         emm::StepParams Pe = A.Pe, Ph = A.Ph;
-        set_tiles(Pe, m, c.tx);
-        set_tiles(Ph, m, c.tx);
+        set_tiles(Pe, m, c.tx, c.ry);
+        set_tiles(Ph, m, c.tx, c.ry);
         Pe.kz = Ph.kz = c.kz;
         Pe.zc = Ph.zc = (nzv + c.kz - 1) / c.kz;
         Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
@@ -1614,7 +1657,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     std::vector<std::pair<float, int>> first;   // (ms, index into tried)
     std::vector<Tune> tried;
     emm_status st;
-    for (int tx : widths)
+    for (auto shape : shapes)
         for (int cp : compacts)
             for (int sh : hints)
                 for (int kz : cand) {
@@ -1622,7 +1665,8 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
                     c.kz = kz;
                     c.stream = sh;
                     c.compact = cp;
-                    c.tx = tx;
+                    c.tx = shape.first;
+                    c.ry = shape.second;
                     float ms = 0.f;
                     if ((st = time_it(c, 6, ms)) != EMM_OK) return st;
                     first.push_back({ms, (int)tried.size()});
@@ -1635,6 +1679,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     pick.stream = A.Pe.stream;
     pick.compact = A.Pe.cei != nullptr;
     pick.tx = A.Pe.tx;
+    pick.ry = A.Pe.ry;
     if (!first.empty()) pick = tried[first[0].second];
     for (size_t c = 0; c < std::min<size_t>(4, first.size()); ++c) {
         float ms = 0.f;
@@ -1649,7 +1694,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     HIP_OK(m, hipGetLastError());
     m->tuned[A.nsrc] = pick;
     for (emm::StepParams *P : {&A.Pe, &A.Ph}) {
-        set_tiles(*P, m, pick.tx);
+        set_tiles(*P, m, pick.tx, pick.ry);
         P->kz = pick.kz;
         P->zc = (nzv + pick.kz - 1) / pick.kz;
         P->nstencil = P->xt * P->yt * P->zc * A.nsrc;
@@ -2048,10 +2093,15 @@ emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm
     PE.r = r;
     PE.nb = nb;
     PE.nsrc = nsrc;
-    PE.kz = A.Pe.kz;                          // z chunks and tile width of the forward kernels
-    PE.tw = A.Pe.tx;
-    PE.xt = A.Pe.xt;
-    PE.yt = A.Pe.yt;
+    // z chunks and tile width of the forward kernels; the gathers' tiles are
+    // one row per wavefront (tw x 256/tw columns), whatever rows per
+    // wavefront the forward kernels used
+    emm::StepParams gt{};
+    set_tiles(gt, m, A.Pe.tx, 1);
+    PE.kz = A.Pe.kz;
+    PE.tw = gt.tx;
+    PE.xt = gt.xt;
+    PE.yt = gt.yt;
     PE.zc = A.Pe.zc;
     PE.nstencil = PE.xt * PE.yt * PE.zc * nsrc;
     PE.fstride = fstride;

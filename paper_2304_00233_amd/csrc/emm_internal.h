@@ -27,6 +27,8 @@ struct StepParams {
     int nb;
     // launch decomposition
     int tx;                     // tile width: 64 (x 4 rows) or 32 (x 8 rows)
+    int ry;                     // rows per wavefront: 1, or 2 / 4 (register-blocked 64-wide
+                                // tiles of 8 / 16 rows, step_kernel_rb)
     int xt, yt, zc, kz;         // x tiles, y tiles, z chunks, planes per chunk
     int kmin;                   // first updated z plane (r, or the surface node under air)
     int nsrc;

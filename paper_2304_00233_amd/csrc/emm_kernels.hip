@@ -390,6 +390,321 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
     }
 }
 
+// Register-blocked variant of step_kernel: a 64-wide tile of 4 RY rows,
+// wavefront w owning rows w RY .. w RY + RY - 1, so every row index is
+// wave-uniform (y coefficients and y-slab CPML values in scalar registers)
+// and each thread updates RY cells per plane.  Per cell it stages
+// (4 RY + 2r - 1)(64 + 2r - 1) / (256 RY) plane values of the x/y-tap
+// component instead of (4 + 2r - 1)(64 + 2r - 1) / 256 (1.6 against 3.0 at
+// r = 4, RY = 4), keeps RY z queues of the two z-differentiated components,
+// and has RY times as many loads in flight per thread.  Each derivative is
+// the same sum in the same order as in step_kernel, so both kernels give the
+// same bits.
+template <int R, bool HS, bool ST, bool CI, int RY>
+__global__ __launch_bounds__(NT) void step_kernel_rb(const StepParams p, int n_arg) {
+    const int n = (p.step_base ? *p.step_base : 0) + n_arg;
+    constexpr int L = 2 * R;
+    constexpr int TX = 64;
+    constexpr int TYS = (NT / TX) * RY;       // rows per tile
+    constexpr int HL = HS ? R - 1 : R;        // halo below the own index
+    constexpr int W = TX + L - 1;             // LDS row length incl. halo
+    constexpr int HR = TYS + L - 1;           // LDS rows incl. halo
+    constexpr int N3 = (HR * W + NT - 1) / NT;              // A3 staging loads per thread
+    constexpr int N1 = ((L - 1) * TX + NT - 1) / NT;        // A1 halo loads per thread
+    constexpr int NC = RY + L - 1;            // y-tap column values a thread's rows read
+    static_assert(TYS * (L - 1) <= NT, "one A2 halo value per thread at most");
+    __shared__ float sA3[2][HR][W];           // x and y taps
+    __shared__ float sA2[2][TYS][W];          // x taps
+    __shared__ float sA1[2][HR][TX];          // y taps
+    __shared__ float sCe[CI ? kCeTable : 1];
+
+    const float *A1 = HS ? p.E1 : p.H1;
+    const float *A2 = HS ? p.E2 : p.H2;
+    const float *A3 = HS ? p.E3 : p.H3;
+
+    const int blk = blockIdx.x;
+    if (blk < p.nrecblk) {
+        rec_dft<R>(p, blk, A1, A2, A3, n);
+        return;
+    }
+    int t = xcd_tile(blk - p.nrecblk, p.nstencil);
+    const int s = t % p.nsrc;
+    t /= p.nsrc;
+    const int bxt = t % p.xt;
+    t /= p.xt;
+    const int byt = t % p.yt;
+    const int bzt = t / p.yt;
+
+    const int tid = threadIdx.x, tx = tid & (TX - 1);
+    const int w0 = __builtin_amdgcn_readfirstlane((tid / TX) * RY);   // first tile row of this wave
+    const int i0 = bxt * TX, j0 = R + byt * TYS;
+    const int i = i0 + tx;
+    const int k0 = p.kmin + bzt * p.kz;
+    const int k1 = min(k0 + p.kz, p.n3 - R);
+    const bool ivalid = i >= R && i <= p.n1 - 1 - R;
+    const long long fo = (long long)s * p.fstride;
+    A1 += fo;
+    A2 += fo;
+    A3 += fo;
+    const int plane = (int)p.plane;
+    const float *U1 = (HS ? p.H1 : p.E1) + fo;
+    const float *U2 = (HS ? p.H2 : p.E2) + fo;
+    const float *U3 = (HS ? p.H3 : p.E3) + fo;
+    float *O1 = (HS ? p.H1 : p.Eo1) + fo;
+    float *O2 = (HS ? p.H2 : p.Eo2) + fo;
+    float *O3 = (HS ? p.H3 : p.Eo3) + fo;
+
+    const float *tx_ = HS ? p.cpx : p.cmx;
+    const float *ty_ = HS ? p.cpy : p.cmy;
+    const float *tz_ = HS ? p.cpz : p.cmz;
+    const int nb = p.nb, nb2 = 2 * p.nb;
+    const int ic = ivalid ? i : R;
+    float cx[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) cx[m] = tx_[ic * L + m];
+    const bool xs = ivalid && (i < nb || i > p.n1 - 1 - nb);
+    float ax = 0.f, bx = 0.f;
+    int ix = 0;
+    if (xs) {
+        ax = (HS ? p.axh : p.axi)[i];
+        bx = (HS ? p.bxh : p.bxi)[i];
+        ix = i < nb ? i : i - (p.n1 - nb2);
+    }
+    // rows of this wavefront (wave-uniform)
+    float cy[RY][L], ay[RY], by[RY];
+    int own[RY], jy[RY];
+    bool rv[RY], ys[RY];
+#pragma unroll
+    for (int q = 0; q < RY; ++q) {
+        const int j = j0 + w0 + q;
+        const int jc = min(j, p.n2 - 1);
+        rv[q] = j <= p.n2 - 1 - R;
+        own[q] = jc * p.pitch + i;
+#pragma unroll
+        for (int m = 0; m < L; ++m) cy[q][m] = ty_[jc * L + m];
+        ys[q] = rv[q] && (j < nb || j > p.n2 - 1 - nb);
+        ay[q] = by[q] = 0.f;
+        jy[q] = 0;
+        if (ys[q]) {
+            ay[q] = (HS ? p.ayh : p.ayi)[j];
+            by[q] = (HS ? p.byh : p.byi)[j];
+            jy[q] = j < nb ? j : j - (p.n2 - nb2);
+        }
+    }
+    const float *az_ = HS ? p.azh : p.azi;
+    const float *bz_ = HS ? p.bzh : p.bzi;
+    float *px0 = p.psx0 + s * p.psxs, *px1 = p.psx1 + s * p.psxs;
+    float *py0 = p.psy0 + s * p.psys, *py1 = p.psy1 + s * p.psys;
+    float *pz0 = p.psz0 + s * p.pszs, *pz1 = p.psz1 + s * p.pszs;
+    const float *ce1 = p.ce1, *ce2 = p.ce2, *ce3 = p.ce3;
+    if (CI && (int)threadIdx.x < p.ncet) sCe[threadIdx.x] = p.cet[threadIdx.x];
+
+    int scomp = -1, sbx = 0, sby = 0, sbz = 0;
+    float sn = 0.f;
+    const float *sq = nullptr;
+    if (!HS) {
+        scomp = p.src_info[4 * s];
+        sbx = p.src_info[4 * s + 1];
+        sby = p.src_info[4 * s + 2];
+        sbz = p.src_info[4 * s + 3];
+        sn = p.wavelet[n];
+        sq = p.src_q + (long long)s * L * L * L;
+    }
+
+    // staging map, as in step_kernel
+    int o3[N3];
+#pragma unroll
+    for (int u = 0; u < N3; ++u) {
+        const int e = tid + u * NT;
+        const int ly = e / W, lx = e - ly * W;
+        const int gj = j0 - HL + ly, gi = i0 - HL + lx;
+        o3[u] = (e < HR * W && gj >= 0 && gj < p.n2 && gi >= 0 && gi < p.pitch) ? gj * p.pitch + gi : -1;
+    }
+    auto ly1 = [&](int u) {
+        const int hy = (tid + u * NT) / TX;
+        return hy < HL ? hy : TYS + hy;
+    };
+    int o1[N1];
+#pragma unroll
+    for (int u = 0; u < N1; ++u) {
+        const int e = tid + u * NT;
+        const int gj = j0 - HL + ly1(u);
+        o1[u] = (e < (L - 1) * TX && gj >= 0 && gj < p.n2) ? gj * p.pitch + i0 + tx : -1;
+    }
+    int o2 = -1, l2 = -1;
+    if (tid < TYS * (L - 1)) {
+        const int hy = tid / (L - 1), hx = tid % (L - 1);
+        const int lx = hx < HL ? hx : TX + hx;
+        const int gi = i0 - HL + lx, gj = min(j0 + hy, p.n2 - 1);
+        l2 = hy * W + lx;
+        o2 = (gi >= 0 && gi < p.pitch) ? gj * p.pitch + gi : -1;
+    }
+
+    float q1[RY][L], q2[RY][L];
+#pragma unroll
+    for (int q = 0; q < RY; ++q)
+#pragma unroll
+        for (int m = 0; m < L - 1; ++m) {
+            q1[q][m] = A1[(unsigned)((k0 - HL + m) * plane + own[q])];
+            q2[q][m] = A2[(unsigned)((k0 - HL + m) * plane + own[q])];
+        }
+
+    float f3[N3], f1[N1], f2 = 0.f, e1n[RY], e2n[RY];
+    float un1[RY], un2[RY], un3[RY], cn1[RY], cn2[RY], cn3[RY];
+    unsigned cin[RY];
+#pragma unroll
+    for (int q = 0; q < RY; ++q) {
+        un1[q] = un2[q] = un3[q] = cn1[q] = cn2[q] = cn3[q] = 0.f;
+        cin[q] = 0u;
+    }
+    auto issue = [&](int k) {
+        const int pk = k * plane;
+#pragma unroll
+        for (int u = 0; u < N3; ++u) f3[u] = o3[u] >= 0 ? A3[(unsigned)(pk + o3[u])] : 0.f;
+#pragma unroll
+        for (int u = 0; u < N1; ++u) f1[u] = o1[u] >= 0 ? A1[(unsigned)(pk + o1[u])] : 0.f;
+        if (o2 >= 0) f2 = A2[(unsigned)(pk + o2)];
+        const int pe = (k - HL + L - 1) * plane;
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            e1n[q] = A1[(unsigned)(pe + own[q])];
+            e2n[q] = A2[(unsigned)(pe + own[q])];
+            if (ivalid && rv[q]) {
+                const unsigned g = (unsigned)(pk + own[q]);
+                un1[q] = ld1<ST>(&U1[g]);
+                un2[q] = ld1<ST>(&U2[g]);
+                un3[q] = ld1<ST>(&U3[g]);
+                if (!HS && CI) {
+                    cin[q] = ld1<ST>(&p.cei[g]);
+                } else if (!HS) {
+                    cn1[q] = ld1<ST>(&ce1[g]);
+                    cn2[q] = ld1<ST>(&ce2[g]);
+                    cn3[q] = ld1<ST>(&ce3[g]);
+                }
+            }
+        }
+    };
+    issue(k0);
+
+    for (int k = k0; k < k1; ++k) {
+        const int b = (k - k0) & 1;
+        float *s3 = &sA3[b][0][0];
+#pragma unroll
+        for (int u = 0; u < N3; ++u)
+            if (u < N3 - 1 || tid + u * NT < HR * W) s3[tid + u * NT] = f3[u];
+        float *s1 = &sA1[b][0][0];
+#pragma unroll
+        for (int u = 0; u < N1; ++u)
+            if (u < N1 - 1 || tid + u * NT < (L - 1) * TX) s1[ly1(u) * TX + tx] = f1[u];
+        if (l2 >= 0) (&sA2[b][0][0])[l2] = o2 >= 0 ? f2 : 0.f;
+        float u1[RY], u2[RY], u3[RY], ce1v[RY], ce2v[RY], ce3v[RY];
+        unsigned ci[RY];
+#pragma unroll
+        for (int q = 0; q < RY; ++q) {
+            q1[q][L - 1] = e1n[q];
+            q2[q][L - 1] = e2n[q];
+            sA2[b][w0 + q][tx + HL] = q2[q][HL];
+            sA1[b][w0 + q + HL][tx] = q1[q][HL];
+            u1[q] = un1[q];
+            u2[q] = un2[q];
+            u3[q] = un3[q];
+            ce1v[q] = cn1[q];
+            ce2v[q] = cn2[q];
+            ce3v[q] = cn3[q];
+            ci[q] = cin[q];
+        }
+        __syncthreads();
+        if (k + 1 < k1) issue(k + 1);
+        if (CI) {
+#pragma unroll
+            for (int q = 0; q < RY; ++q) {
+                ce1v[q] = sCe[ci[q] & 255u];
+                ce2v[q] = sCe[(ci[q] >> 8) & 255u];
+                ce3v[q] = sCe[(ci[q] >> 16) & 255u];
+            }
+        }
+        if (ivalid) {
+            const float *cz = tz_ + k * L;
+            // the y-tap columns of this thread's rows, read from LDS once
+            float c3[NC], c1[NC];
+#pragma unroll
+            for (int u = 0; u < NC; ++u) {
+                c3[u] = sA3[b][w0 + u][tx + HL];
+                c1[u] = sA1[b][w0 + u][tx];
+            }
+            const bool zs = k < nb || k > p.n3 - 1 - nb;
+            const int kz = k < nb ? k : k - (p.n3 - nb2);
+            const float az = zs ? az_[k] : 0.f, bz = zs ? bz_[k] : 0.f;
+#pragma unroll
+            for (int q = 0; q < RY; ++q) {
+                if (!rv[q]) continue;
+                const int j = j0 + w0 + q;
+                float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
+#pragma unroll
+                for (int m = 0; m < L; ++m) {
+                    d2a3 += cy[q][m] * c3[q + m];
+                    d2a1 += cy[q][m] * c1[q + m];
+                    d1a3 += cx[m] * sA3[b][w0 + q + HL][tx + m];
+                    d1a2 += cx[m] * sA2[b][w0 + q][tx + m];
+                    d3a2 += cz[m] * q2[q][m];
+                    d3a1 += cz[m] * q1[q][m];
+                }
+                if (xs) {
+                    const unsigned id = (unsigned)((k * p.n2 + j) * nb2 + ix);
+                    float v = bx * px0[id] + ax * d1a3;
+                    px0[id] = v;
+                    d1a3 += v;
+                    v = bx * px1[id] + ax * d1a2;
+                    px1[id] = v;
+                    d1a2 += v;
+                }
+                if (ys[q]) {
+                    const unsigned id = (unsigned)((k * nb2 + jy[q]) * p.pitch + i);
+                    float v = by[q] * py0[id] + ay[q] * d2a3;
+                    py0[id] = v;
+                    d2a3 += v;
+                    v = by[q] * py1[id] + ay[q] * d2a1;
+                    py1[id] = v;
+                    d2a1 += v;
+                }
+                if (zs) {
+                    const unsigned id = (unsigned)((kz * p.n2 + j) * p.pitch + i);
+                    float v = bz * pz0[id] + az * d3a2;
+                    pz0[id] = v;
+                    d3a2 += v;
+                    v = bz * pz1[id] + az * d3a1;
+                    pz1[id] = v;
+                    d3a1 += v;
+                }
+                float r1 = d2a3 - d3a2, r2 = d3a1 - d1a3, r3 = d1a2 - d2a1;
+                const unsigned g = (unsigned)(k * plane + own[q]);
+                if (HS) {
+                    st1<ST>(&O1[g], u1[q] - p.ch * r1);
+                    st1<ST>(&O2[g], u2[q] - p.ch * r2);
+                    st1<ST>(&O3[g], u3[q] - p.ch * r3);
+                } else {
+                    if (k >= sbz && k < sbz + L && j >= sby && j < sby + L && i >= sbx && i < sbx + L) {
+                        const float jv = sn * sq[((k - sbz) * L + (j - sby)) * L + (i - sbx)];
+                        if (scomp == 0) r1 -= jv;
+                        else if (scomp == 1) r2 -= jv;
+                        else r3 -= jv;
+                    }
+                    st1<ST>(&O1[g], u1[q] + ce1v[q] * r1);
+                    st1<ST>(&O2[g], u2[q] + ce2v[q] * r2);
+                    st1<ST>(&O3[g], u3[q] + ce3v[q] * r3);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RY; ++q)
+#pragma unroll
+            for (int m = 0; m < L - 1; ++m) {
+                q1[q][m] = q1[q][m + 1];
+                q2[q][m] = q2[q][m + 1];
+            }
+    }
+}
+
 // Fused leap-frog step: one launch per time step reads E^n, H^{n+1/2} and
 // dt/eps once and writes E^{n+1}, H^{n+3/2} to the other buffers of a
 // ping-pong pair (60 B per cell and step instead of 84 for the two half-step
@@ -745,7 +1060,15 @@ void launch_leap(int r, const StepParams &pe, const StepParams &ph, const LeapPa
 template <int R, bool HS, bool ST, bool CI>
 static void launch_r(const StepParams &p, int n, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const dim3 grid(p.nrecblk + p.nstencil), block(NT);
-    if (p.tx == 32) {
+    if (p.ry == 2 || p.ry == 4) {
+        if (p.ry == 2) {
+            if (t0 || t1) hipExtLaunchKernelGGL((step_kernel_rb<R, HS, ST, CI, 2>), grid, block, 0, s, t0, t1, 0, p, n);
+            else hipLaunchKernelGGL((step_kernel_rb<R, HS, ST, CI, 2>), grid, block, 0, s, p, n);
+        } else {
+            if (t0 || t1) hipExtLaunchKernelGGL((step_kernel_rb<R, HS, ST, CI, 4>), grid, block, 0, s, t0, t1, 0, p, n);
+            else hipLaunchKernelGGL((step_kernel_rb<R, HS, ST, CI, 4>), grid, block, 0, s, p, n);
+        }
+    } else if (p.tx == 32) {
         if (t0 || t1) hipExtLaunchKernelGGL((step_kernel<R, HS, ST, CI, 32>), grid, block, 0, s, t0, t1, 0, p, n);
         else hipLaunchKernelGGL((step_kernel<R, HS, ST, CI, 32>), grid, block, 0, s, p, n);
     } else {

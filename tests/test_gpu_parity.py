@@ -103,9 +103,16 @@ def test_bitwise_determinism_runs_and_tiles(emm, rd):
     G4, i4 = _run(emm, w, tile_x=32, tile_kz=7, ce_table=1)
     G5, i5 = _run(emm, w, tile_x=64, ce_table=0)
     G6, i6 = _run(emm, w, tile_x=32, ce_table=0, nontemporal=1)
+    # register-blocked 64 x 8 and 64 x 16 tiles (two and four rows per wavefront;
+    # the 30-row y extent leaves a ragged last tile of each)
+    G7, i7 = _run(emm, w, tile_rows=2, ce_table=1, tile_kz=5)
+    G8, i8 = _run(emm, w, tile_rows=4, ce_table=0, nontemporal=1)
+    G9, i9 = _run(emm, w, tile_rows=4, ce_table=1)
     assert i3["tile_kz"] == 3 and (i4["tile_x"], i5["tile_x"], i6["tile_x"]) == (32, 64, 32)
     assert (i4["ce_table"], i5["ce_table"], i6["ce_table"]) == (1, 0, 0)
-    for G in (G2, G3, G4, G5, G6):
+    assert (i7["tile_rows"], i8["tile_rows"], i9["tile_rows"]) == (2, 4, 4)
+    assert (i7["tile_x"], i8["tile_x"], i9["tile_x"]) == (64, 64, 64)
+    for G in (G2, G3, G4, G5, G6, G7, G8, G9):
         assert np.array_equal(G1, G)
 
 

@@ -158,6 +158,45 @@ def towline_sources(count: int = 16, spacing: float = 500.0, z: float = 950.0):
     return np.stack([xs, np.zeros_like(xs), np.full_like(xs, z)], axis=1)
 
 
+def towline_small(count: int = 16, spacing: float = 250.0) -> Workload:
+    """`count` x-dipoles every `spacing` m along the x axis (y = z = 0) of
+    the 48^3 plain-forward model: the towline of a multi-transmitter survey
+    on a grid small enough (82^3 padded cells) that one source alone leaves
+    most of the chip idle.  16 at 250 m span x = -1875..1875."""
+    w = plain_forward()
+    xs = spacing * (np.arange(count) - 0.5 * (count - 1))
+    src = np.stack([xs, np.zeros_like(xs), np.zeros_like(xs)], axis=1)
+    return w.with_(name=f"towline_{count}x{spacing:g}m_48cube", sources=src,
+                   src_comp=np.zeros(count, dtype=np.int32))
+
+
+def differentiation_48cube(nt: int = 0) -> tuple:
+    """The misfit-gradient workload: the 48^3 plain-forward model (1 ohm-m,
+    100 m cells) as the prediction, and the same grid with a 200 ohm-m box
+    (|x|, |y| <= 500 m, 300 <= z <= 500 m) as the model that makes the
+    observed data; the x-dipole at the origin, the 21 inline receivers, Ex
+    only, 0.25 / 0.75 / 1.25 Hz.  Returns (prediction, observed-data model)."""
+    w = plain_forward(nt=nt)
+    w = w.with_(name="differentiation_48cube", chan_mask=1, freqs=np.array([0.25, 0.75, 1.25]))
+    m = BlockModel(background=1.0)
+    m.add_box(-500.0, 500.0, -500.0, 500.0, 300.0, 500.0, 200.0)
+    r11, r22, r33 = _model_arrays(m, w.x1, w.x2, w.x3)
+    return w, w.with_(name="differentiation_48cube_box", rho11=r11, rho22=r22, rho33=r33)
+
+
+def interior_cells(w, count: int, seed: int, margin: int = 2, weight=None) -> np.ndarray:
+    """`count` distinct (component, k, j, i) cells of the input grid, at
+    least `margin` nodes inside every face, drawn with numpy's default_rng
+    (seed); with `weight` ([3][n3][n2][n1], >= 0) the draw is weighted by it."""
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = w.shape
+    mask = np.zeros((3, n3, n2, n1), dtype=bool)
+    mask[:, margin:n3 - margin, margin:n2 - margin, margin:n1 - margin] = True
+    p = mask.astype(np.float64) if weight is None else mask * np.asarray(weight, dtype=np.float64)
+    flat = rng.choice(p.size, size=count, replace=False, p=p.ravel() / p.sum())
+    return np.stack(np.unravel_index(flat, p.shape), axis=1)
+
+
 # --------------------------------------------------------------------------
 # Random layered + box models (seeded), uniform 100 m grid.
 # --------------------------------------------------------------------------
