@@ -216,6 +216,30 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc,
                        const double *freq_hz, int nfreq, double *green,
                        void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): emm_forward with the
+ * same arguments, results and errors, whose per-call device buffers (fields,
+ * CPML memories, DTFT accumulators, source / receiver / CPML / phase tables)
+ * all live in one static device workspace of 128 MiB per device (held from
+ * the library's first use on a device until the process ends); it calls no
+ * hipMalloc / hipFree, creates no event or graph, and clears what must start
+ * at zero with a fill kernel.  It runs every source in one time loop of
+ * direct launches (graph_steps and profile are ignored for the call; tiles:
+ * the model's option or earlier autotuned choice, no autotuning).  A call
+ * whose buffers exceed 128 MiB fails with EMM_ERR_OOM and a message giving
+ * the bytes it needs (about 30 MB per source on a 48^3 grid with 10 CPML
+ * layers); the air boundary and checkpoints (options airwave,
+ * checkpoint_every) are refused with EMM_ERR_ARG.  The model itself must
+ * exist (emm_create allocates its arrays once).  All calls on one device
+ * share its workspace: calls that overlap in time on one device (any
+ * models, any host threads or streams) race and give wrong results; the
+ * workspace keeps the last call's contents.  A following emm_gradient does
+ * not reuse anything from this call. */
+emm_status emm_forward_noalloc(emm_model *m, const emm_source *src, int nsrc,
+                               const emm_receiver *rec, int nrec, unsigned chan_mask,
+                               const double *freq_hz, int nfreq, double *green,
+                               void *hip_stream);
+
 /* One forward modelling of emm_forward_batch: a model with its acquisition
  * and output, all as in emm_forward. */
 typedef struct {

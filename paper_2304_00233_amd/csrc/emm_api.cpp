@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <string>
@@ -32,7 +33,39 @@ thread_local std::string g_last_error;
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;     // carved from the static workspace: never freed
 };
+
+// Static device workspace of emm_forward_noalloc (callers that cannot
+// allocate device memory): every per-call buffer of such a forward (fields,
+// CPML memories, DTFT accumulators, source, receiver, CPML and phase tables)
+// is carved from it.  Each device that loads the library holds its own copy
+// until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchSlot {
+    bool done = false;
+    hipError_t err = hipSuccess;
+    void *ptr = nullptr;
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchSlot> g_scratch;
+
+// Once per device, with that device current: the device address of its copy
+// of `scratch`.
+hipError_t scratch_address(int device, void **ptr) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchSlot &slot = g_scratch[device];
+    if (!slot.done) {
+        slot.err = hipGetSymbolAddress(&slot.ptr, HIP_SYMBOL(scratch));
+        if (slot.err != hipSuccess) slot.ptr = nullptr;
+        slot.done = true;
+    }
+    *ptr = slot.ptr;
+    return slot.err;
+}
 
 }  // namespace
 
@@ -101,6 +134,12 @@ struct emm_model {
     std::unique_ptr<emm::AirBoundary> air;          // ghost planes above the surface (airwave)
     hipEvent_t ev_loop[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ring;       // profiling: start/end pairs
+    // static workspace of emm_forward_noalloc on this model's device
+    void *scratch = nullptr;
+    hipError_t scratch_err = hipSuccess;
+    // set only during emm_forward_noalloc: ensure() carves from here
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
     emm_info info{};
     std::string err;
 };
@@ -124,7 +163,25 @@ emm_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? EMM_ERR_
     } while (0)
 
 emm_status ensure(emm_model *m, DevBuf &b, size_t bytes) {
-    if (b.bytes >= bytes && b.p) return EMM_OK;
+    if (m->arena) {
+        // no-alloc call: the next 256-byte aligned piece of the static workspace
+        const size_t need = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        if (m->arena_used + need > m->arena_cap)
+            return fail(m, EMM_ERR_OOM, "the forward needs more than the " + std::to_string(m->arena_cap) +
+                                            "-byte static workspace of emm_forward_noalloc (" +
+                                            std::to_string(m->arena_used + need) + " bytes so far)");
+        b.p = m->arena + m->arena_used;
+        b.bytes = bytes;
+        b.borrowed = true;
+        m->arena_used += need;
+        return EMM_OK;
+    }
+    if (b.bytes >= bytes && b.p && !b.borrowed) return EMM_OK;
+    if (b.p && b.borrowed) {
+        b.p = nullptr;
+        b.bytes = 0;
+        b.borrowed = false;
+    }
     if (b.p) {
         (void)hipFree(b.p);
         b.p = nullptr;
@@ -331,7 +388,7 @@ void emm_destroy(emm_model *m) {
     for (DevBuf *b : {&m->fields, &m->psi, &m->acc, &m->cpml, &m->srcinfo, &m->srcq, &m->wav,
                       &m->items, &m->itemw, &m->phase, &m->fieldsB, &m->psiB, &m->ckpts, &m->ickpts, &m->adjf, &m->adjq, &m->adjt,
                       &m->snaps, &m->grad, &m->grad32, &m->tabT, &m->inj, &m->injA, &m->adjcpml, &m->stepdev})
-        if (b->p) (void)hipFree(b->p);
+        if (b->p && !b->borrowed) (void)hipFree(b->p);
     for (hipEvent_t e : m->ev_loop) if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : m->ring) if (e) (void)hipEventDestroy(e);
     if (m->own_stream) (void)hipStreamDestroy(m->own_stream);
@@ -465,6 +522,9 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     {
         hipError_t e = hipGetDevice(&m->device);
         if (e == hipSuccess) e = hipStreamCreate(&m->own_stream);
+        // set-up of the static workspace of emm_forward_noalloc on this device
+        // (a failure is reported by that call, not here)
+        if (e == hipSuccess) m->scratch_err = scratch_address(m->device, &m->scratch);
         if (e != hipSuccess) {
             emm_status s = fail(nullptr, EMM_ERR_DEVICE, std::string("device set-up: ") + hipGetErrorString(e));
             delete m;
@@ -1081,6 +1141,15 @@ emm_status zero_state(emm_model *m, hipStream_t stream) {
     const size_t fbytes = (size_t)6 * A.nsrc * fstride * sizeof(float);
     const size_t psi_bytes = (state_floats(m) - 6 * fstride) * A.nsrc * sizeof(float);
     const size_t abytes = (size_t)nslot * A.nf * acc_elem;
+    if (m->arena) {
+        // the static workspace keeps the last call's contents; cleared with a
+        // fill kernel (no memset node if the caller captures the stream)
+        emm::launch_zero(m->fields.p, fbytes, stream);
+        if (psi_bytes) emm::launch_zero(m->psi.p, psi_bytes, stream);
+        emm::launch_zero(m->acc.p, abytes, stream);
+        HIP_OK(m, hipGetLastError());
+        return EMM_OK;
+    }
     HIP_OK(m, hipMemsetAsync(m->fields.p, 0, fbytes, stream));
     if (psi_bytes) HIP_OK(m, hipMemsetAsync(m->psi.p, 0, psi_bytes, stream));
     HIP_OK(m, hipMemsetAsync(m->acc.p, 0, abytes, stream));
@@ -1126,7 +1195,8 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         const long long timed_max = blocks * ((Kg + 3) / 4) + (nt + sample - 1) / sample + 1;
         if ((st = ensure_events(m, (size_t)(4 * timed_max))) != EMM_OK) return st;
     }
-    if (!m->ev_loop[0]) {
+    const bool loop_events = !m->arena;     // a no-alloc call creates no events
+    if (loop_events && !m->ev_loop[0]) {
         HIP_OK(m, hipEventCreate(&m->ev_loop[0]));
         HIP_OK(m, hipEventCreate(&m->ev_loop[1]));
     }
@@ -1199,7 +1269,7 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         }
         return EMM_OK;
     };
-    HIP_OK(m, hipEventRecord(m->ev_loop[0], stream));
+    if (loop_events) HIP_OK(m, hipEventRecord(m->ev_loop[0], stream));
     int n_begin = 0;
     // K steps per captured hipGraph, replayed with a device step counter;
     // checkpoints and convergence checks must fall on replay edges
@@ -1266,13 +1336,13 @@ emm_status time_loop(emm_model *m, hipStream_t stream, int ckpt) {
         }
     }
     HIP_OK(m, hipGetLastError());
-    HIP_OK(m, hipEventRecord(m->ev_loop[1], stream));
+    if (loop_events) HIP_OK(m, hipEventRecord(m->ev_loop[1], stream));
     if (prof)
         for (int u = 0; u < nslots_used; ++u)
             if ((st = harvest(u)) != EMM_OK) return st;
     HIP_OK(m, hipStreamSynchronize(stream));
     float loop_ms = 0.f;
-    HIP_OK(m, hipEventElapsedTime(&loop_ms, m->ev_loop[0], m->ev_loop[1]));
+    if (loop_events) HIP_OK(m, hipEventElapsedTime(&loop_ms, m->ev_loop[0], m->ev_loop[1]));
     A.ckpt = converged ? 0 : ckpt;
     m->info.nt = n_done;
     m->info.converged = converged ? 1 : 0;
@@ -1748,6 +1818,51 @@ emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc, const emm_
     m->info.e_launches = e_n;
     m->info.h_launches = h_n;
     m->info.src_group = g;
+    return EMM_OK;
+}
+
+emm_status emm_forward_noalloc(emm_model *m, const emm_source *src, int nsrc,
+                               const emm_receiver *rec, int nrec, unsigned chan_mask,
+                               const double *freq_hz, int nfreq, double *green, void *hip_stream) {
+    if (!m) return fail(nullptr, EMM_ERR_ARG, "NULL model");
+    m->err.clear();
+    if (!green) return fail(m, EMM_ERR_ARG, "NULL output pointer");
+    if (m->opt.airwave || m->opt.checkpoint_every > 0)
+        return fail(m, EMM_ERR_ARG, "emm_forward_noalloc runs neither the air boundary nor "
+                                    "checkpointed forwards (their buffers need allocation)");
+    if (m->scratch_err != hipSuccess || !m->scratch)
+        return fail(m, EMM_ERR_DEVICE, std::string("static workspace address: ") + hipGetErrorString(m->scratch_err));
+    hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : m->own_stream;
+    // the forward-lifetime buffers of earlier emm_forward calls stay aside
+    // (and allocated) while this call carves its own from the workspace
+    DevBuf *bufs[] = {&m->fields, &m->psi, &m->acc, &m->cpml, &m->srcinfo, &m->srcq,
+                      &m->wav, &m->items, &m->itemw, &m->phase, &m->stepdev};
+    constexpr int kBufs = sizeof(bufs) / sizeof(bufs[0]);
+    DevBuf saved[kBufs];
+    for (int b = 0; b < kBufs; ++b) {
+        saved[b] = *bufs[b];
+        *bufs[b] = DevBuf{};
+    }
+    const emm_options opt_saved = m->opt;
+    m->opt.graph_steps = 0;        // direct launches: no graph to instantiate
+    m->opt.profile = 0;            // no timing events
+    m->arena = (char *)m->scratch;
+    m->arena_cap = kScratchBytes;
+    m->arena_used = 0;
+    emm_status st = prepare(m, src, nsrc, rec, nrec, chan_mask, freq_hz, nfreq, stream);
+    if (st == EMM_OK) st = time_loop(m, stream, 0);
+    if (st == EMM_OK) st = write_green(m, stream, green);
+    if (st != EMM_OK) (void)hipStreamSynchronize(stream);
+    m->arena = nullptr;
+    m->arena_cap = m->arena_used = 0;
+    m->opt = opt_saved;
+    for (int b = 0; b < kBufs; ++b) *bufs[b] = saved[b];
+    m->acq.valid = false;          // its parameters point into the workspace
+    m->acq.ckpt = 0;
+    if (st != EMM_OK) return st;
+    m->info.src_group = nsrc;
+    m->info.e_kernel_ms = m->info.h_kernel_ms = 0.0;
+    m->info.e_launches = m->info.h_launches = 0;
     return EMM_OK;
 }
 

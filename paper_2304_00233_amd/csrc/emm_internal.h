@@ -107,5 +107,7 @@ void launch_advance(int *step, int k, hipStream_t s);
 void launch_h_step(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t t0 = nullptr,
                    hipEvent_t t1 = nullptr);
 int block_threads();
+// zero `bytes` (a multiple of 4) at p, 4-byte aligned, with a fill kernel
+void launch_zero(void *p, size_t bytes, hipStream_t s);
 
 }  // namespace emm

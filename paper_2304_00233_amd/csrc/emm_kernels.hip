@@ -31,6 +31,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 namespace emm {
 
 constexpr int TY = kTileY;
@@ -1095,6 +1097,24 @@ void launch_e_step(int r, const StepParams &p, int n, hipStream_t s, hipEvent_t 
         if (p.stream) launch<false, true, false>(r, p, n, s, t0, t1);
         else launch<false, false, false>(r, p, n, s, t0, t1);
     }
+}
+
+// zero n 4-byte words: 16-byte stores for the aligned bulk, then the tail
+__global__ __launch_bounds__(256) void zero_kernel(unsigned *p, size_t n) {
+    const size_t n4 = n / 4;
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+        q[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t i = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
+void launch_zero(void *p, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 4;
+    if (n == 0) return;
+    const size_t want = (n / 4 + 255) / 256;
+    const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>(want, 4096));
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, s, (unsigned *)p, n);
 }
 
 // graph replays: advance the device step counter by k after each replay

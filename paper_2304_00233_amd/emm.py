@@ -24,8 +24,8 @@ STATUS = {0: "EMM_OK", -1: "EMM_ERR_ARG", -2: "EMM_ERR_GRID", -3: "EMM_ERR_MODEL
           -4: "EMM_ERR_GEOMETRY", -5: "EMM_ERR_FREQ", -6: "EMM_ERR_CFL",
           -7: "EMM_ERR_NONFINITE", -8: "EMM_ERR_OOM", -9: "EMM_ERR_DEVICE"}
 EXPORTED = ("emm_default_options", "emm_create", "emm_query", "emm_forward",
-            "emm_forward_batch", "emm_gradient", "emm_destroy", "emm_status_str",
-            "emm_last_error")
+            "emm_forward_noalloc", "emm_forward_batch", "emm_gradient", "emm_destroy",
+            "emm_status_str", "emm_last_error")
 
 _dp = C.POINTER(C.c_double)
 _fp = C.POINTER(C.c_float)
@@ -98,6 +98,8 @@ def _load():
                                 C.POINTER(emm_receiver), C.c_int, C.c_uint, _dp, C.c_int,
                                 _dp, C.c_void_p]
     lib.emm_forward.restype = C.c_int
+    lib.emm_forward_noalloc.argtypes = lib.emm_forward.argtypes
+    lib.emm_forward_noalloc.restype = C.c_int
     lib.emm_forward_batch.argtypes = [C.POINTER(emm_job), C.c_int, C.c_int, C.c_void_p]
     lib.emm_forward_batch.restype = C.c_int
     lib.emm_gradient.argtypes = [C.c_void_p, C.POINTER(emm_source), C.c_int,
@@ -164,9 +166,11 @@ def emm_query(model) -> emm_info:
 
 
 def emm_forward(model, sources, receivers, chan_mask: int, freqs, src_comp=None,
-                moments=None, stream=None) -> np.ndarray:
+                moments=None, stream=None, noalloc: bool = False) -> np.ndarray:
     """sources [nsrc][3], receivers [nrec][3] in metres; returns complex128
-    [nsrc][nrec][popcount(chan_mask)][nfreq]."""
+    [nsrc][nrec][popcount(chan_mask)][nfreq].  noalloc: call
+    emm_forward_noalloc (per-call buffers in the library's static device
+    workspace) instead of emm_forward."""
     sources = np.atleast_2d(np.asarray(sources, dtype=np.float64))
     receivers = np.atleast_2d(np.asarray(receivers, dtype=np.float64))
     freqs = np.ascontiguousarray(freqs, dtype=np.float64)
@@ -178,9 +182,9 @@ def emm_forward(model, sources, receivers, chan_mask: int, freqs, src_comp=None,
     R = (emm_receiver * max(nr, 1))(*[emm_receiver(*receivers[i]) for i in range(nr)])
     nch = bin(chan_mask & 0x3F).count("1")
     out = np.zeros(2 * max(ns, 1) * max(nr, 1) * max(nch, 1) * max(nf, 1))
-    _check(_lib.emm_forward(model, S, ns, R, nr, C.c_uint(chan_mask),
-                            freqs.ctypes.data_as(_dp), nf, out.ctypes.data_as(_dp),
-                            stream), model)
+    fn = _lib.emm_forward_noalloc if noalloc else _lib.emm_forward
+    _check(fn(model, S, ns, R, nr, C.c_uint(chan_mask), freqs.ctypes.data_as(_dp), nf,
+              out.ctypes.data_as(_dp), stream), model)
     g = out[0::2] + 1j * out[1::2]
     return g.reshape(ns, nr, nch, nf)
 
@@ -286,14 +290,14 @@ class Model:
         self.h = emm_create(w.x1, w.x2, w.x3, w.rho11, w.rho22, w.rho33, self.opts)
 
     def forward(self, sources=None, receivers=None, freqs=None, chan_mask=None,
-                src_comp=None, stream=None) -> np.ndarray:
+                src_comp=None, stream=None, noalloc: bool = False) -> np.ndarray:
         w = self.w
         return emm_forward(self.h, w.sources if sources is None else sources,
                            w.receivers if receivers is None else receivers,
                            w.chan_mask if chan_mask is None else chan_mask,
                            w.freqs if freqs is None else freqs,
                            w.src_comp if src_comp is None and sources is None else src_comp,
-                           stream=stream)
+                           stream=stream, noalloc=noalloc)
 
     def gradient(self, g_obs=None, g_bar=None, sources=None, receivers=None, freqs=None,
                  chan_mask=None, src_comp=None, stream=None):

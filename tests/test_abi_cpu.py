@@ -137,6 +137,7 @@ def test_null_pointers(emm):
     assert lib.emm_default_options(None) == -1
     assert lib.emm_query(None, None) == -1
     assert lib.emm_forward(None, None, 0, None, 0, 0, None, 0, None, None) == -1
+    assert lib.emm_forward_noalloc(None, None, 0, None, 0, 0, None, 0, None, None) == -1
     assert lib.emm_forward_batch(None, 1, 0, None) == -1
     jobs = (emm.emm_job * 2)()
     assert lib.emm_forward_batch(jobs, 0, 0, None) == -1      # no jobs
