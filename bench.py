@@ -36,12 +36,23 @@ SHALLOW_GOLDEN = os.path.join(ROOT, "tests", "golden", "shallow_marine_air_oracl
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE (x 2.0) and WRITE_SIZE
 # (x 1.0), the factors from a 1 GiB copy kernel, keyed by workload, kernel and
-# launch configuration (tile width, rows per wavefront, z planes per block,
-# nontemporal hint, compact dt/eps, sources).  A run whose autotuned launch
+# launch configuration (tile width, rows per wavefront, source order,
+# nontemporal hint, compact dt/eps, sources; the z chunk length, which the
+# autotuner varies between runs, moves it by the queue prologue of the chunk,
+# (2r - 1)/kz of two arrays, ~1 % here).  A run whose autotuned launch
 # differs reports null: the counters belong to the kernel as profiled.
 TRAFFIC_KIB = {
-    # (workload, kernel, tx, ry, kz, nontemporal, compact, nsrc): (FETCH_SIZE KiB, WRITE_SIZE KiB)
-    ("marine_layered_128x128x96", "e_step", 32, 1, 5, 0, 1, 1): (54421.1, 46143.4),
+    # (workload, kernel, tx, ry, source order, nontemporal, compact, nsrc):
+    #     (FETCH_SIZE KiB, WRITE_SIZE KiB); the large grid at 8th order with 8
+    #     sources, 58 z planes per block (profiles/step_kernel_large_marine_*)
+    ("large_marine_400x400x200", "e_step", 32, 1, 1, 0, 1, 8): (6547920.6, 4451655.2),
+    ("large_marine_400x400x200", "h_step", 32, 1, 1, 0, 1, 8): (5861969.3, 4450456.0),
+    ("large_marine_400x400x200", "e_step", 64, 1, 1, 0, 1, 8): (6789607.5, 4450503.2),
+    ("large_marine_400x400x200", "h_step", 64, 1, 1, 0, 1, 8): (6024722.6, 4444159.0),
+    ("large_marine_400x400x200", "e_step", 32, 1, 1, 1, 1, 8): (5879356.1, 4445875.8),
+    ("large_marine_400x400x200", "h_step", 32, 1, 1, 1, 1, 8): (5231072.4, 4445578.2),
+    ("large_marine_400x400x200", "e_step", 64, 1, 1, 1, 1, 8): (5873905.4, 4428338.8),
+    ("large_marine_400x400x200", "h_step", 64, 1, 1, 1, 1, 8): (5221831.9, 4426978.2),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -141,7 +152,7 @@ def kernel_bytes(info, nsrc):
 
 
 def traffic(workload, kernel, info, nsrc):
-    key = (workload, kernel, info["tile_x"], info.get("tile_rows", 1), info["tile_kz"],
+    key = (workload, kernel, info["tile_x"], info["tile_rows"], info["src_order"],
            info["nontemporal"], info["ce_table"], nsrc)
     kib = TRAFFIC_KIB.get(key)
     if kib is None:
@@ -356,6 +367,10 @@ def main():
     ap.add_argument("--tile-kz", type=int, default=-1, help="z planes per block (-1: autotuned)")
     ap.add_argument("--tile-x", type=int, default=0, choices=(0, 32, 64))
     ap.add_argument("--tile-rows", type=int, default=0, choices=(0, 1, 2, 4))
+    ap.add_argument("--nontemporal", type=int, default=-1, choices=(-1, 0, 1),
+                    help="nontemporal hints on the arrays a launch touches once (-1: autotuned)")
+    ap.add_argument("--src-order", type=int, default=-1, choices=(-1, 0, 1),
+                    help="tile order of the sources (-1: autotuned)")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed steps (no batched, accuracy, marine, towline legs)")
     ap.add_argument("--multi-model", action="store_true",
@@ -425,7 +440,8 @@ def main():
     log(f"[bench] workload {w.name} padded cells {w.padded_cells} sources {nsrc}")
 
     model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz, fused=args.fused,
-                      tile_x=args.tile_x, tile_rows=args.tile_rows)
+                      tile_x=args.tile_x, tile_rows=args.tile_rows, src_order=args.src_order,
+                      nontemporal=args.nontemporal)
     wall, acc, info = timed_forwards(model, args.steps, args.warmup, "main")
     model.close()
     nt = info["nt"]
@@ -444,7 +460,8 @@ def main():
     log(f"[bench] nt={nt} wall/step={ms_per_step:.1f} ms device loop/step="
         f"{acc['dev_ms'] / args.steps:.1f} ms e_step avg={e_avg_s * 1e6:.2f} us "
         f"h_step avg={h_avg_s * 1e6:.2f} us tile_kz={info['tile_kz']} tile_x={info['tile_x']} "
-        f"tile_rows={info['tile_rows']} nontemporal={info['nontemporal']} ce_table={info['ce_table']}")
+        f"tile_rows={info['tile_rows']} src_order={info['src_order']} nontemporal={info['nontemporal']} "
+        f"ce_table={info['ce_table']}")
     step_desc = (f"one forward of the {nsrc} sources batched, over a window of {nt} time steps "
                  f"(of the {18800} of a converged run)" if large else
                  "one full forward modelling (nt time steps)")
@@ -471,8 +488,8 @@ def main():
         "interior_gcell_step_per_s": (len(w.x1) * len(w.x2) * len(w.x3)) * nt * nsrc * args.steps / wall / 1e9,
         "device_loop_ms_per_step": acc["dev_ms"] / args.steps,
         "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"], "tile_rows": info["tile_rows"],
-                   "nontemporal": info["nontemporal"], "compact_dt_eps": info["ce_table"],
-                   "graph_steps": args.graph},
+                   "src_order": info["src_order"], "nontemporal": info["nontemporal"],
+                   "compact_dt_eps": info["ce_table"], "graph_steps": args.graph},
     }
     if not fused:
         out["h_step"] = {"bytes_per_launch": kb["h"], "avg_launch_us": h_avg_s * 1e6,

@@ -135,6 +135,12 @@ typedef struct {
                               per cell, more loads per thread, but 2-3 waves per SIMD; needs
                               tile_x 0 or 64); 0 = 1, and the autotuner (tile_kz = -1) then
                               tries only the one-row shapes.  Every shape gives the same bits [0] */
+    int    src_order;      /* order of the stencil blocks of several sources in one launch: 0 =
+                              source fastest (the blocks of all sources for one spatial tile run
+                              together and share dt/eps through L2), 1 = source slowest (each XCD
+                              streams whole sources, so neighbouring tiles of one source share their
+                              halos in L2); -1 = autotuned with tile_kz = -1, else 0.  Both give
+                              the same bits [-1] */
 } emm_options;
 
 /* A point electric dipole (the acquisition of Section 5): position in
@@ -172,6 +178,7 @@ typedef struct {
                                 after emm_forward_batch) */
     int    tile_x;           /* columns per block of the last forward's stencil kernels */
     int    tile_rows;        /* grid rows per wavefront of the last forward's stencil kernels */
+    int    src_order;        /* tile order of the sources in the last forward's launches */
 } emm_info;
 
 /* Fill *o with the defaults above: the paper's values where it states them

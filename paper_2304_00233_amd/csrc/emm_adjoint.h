@@ -12,6 +12,7 @@ struct AdjParams {
     int kz;                       // z planes per thread block of the gathers
     int tw;                       // tile width of the gathers: 64 (x 4 rows) or 32 (x 8 rows)
     int xt, yt, zc, nstencil;     // tiles along x, y, z chunks; xt * yt * zc * nsrc
+    int sorder;                   // tile order of the sources (StepParams::sorder)
     long long fstride;            // one source's field array (plane * n3)
     // inputs (filtered by the CPML reverse) and outputs of the gather,
     // source 0 (source s at + s * fstride)

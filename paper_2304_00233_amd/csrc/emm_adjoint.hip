@@ -132,8 +132,7 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
     if (CI && (int)threadIdx.x < p.ncet) sCe[threadIdx.x] = p.cet[threadIdx.x];
 
     int t = xcd_tile(blockIdx.x, p.nstencil);
-    const int s = t % p.nsrc;
-    t /= p.nsrc;
+    const int s = tile_source(t, p.nsrc, p.nstencil, p.sorder);
     const int bxt = t % p.xt;
     t /= p.xt;
     const int byt = t % p.yt;
@@ -210,6 +209,8 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
 
     float f3x[NX], f2x[NX], f3y[NY], f1y[NY], e1n = 0.f, e2n = 0.f;
     float o1 = 0.f, o2 = 0.f, o3 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
+    float gn1 = 0.f, gn2 = 0.f, gn3 = 0.f;           // FP32 gradient partial sums (reverse of the E update)
+    float xa1 = 0.f, xa2 = 0.f, xa3 = 0.f, xn1 = 0.f, xn2 = 0.f, xn3 = 0.f, xp1 = 0.f, xp2 = 0.f, xp3 = 0.f;
     unsigned wi = 0;
     auto issue = [&](int k) {
         const int pk = k * plane;
@@ -237,10 +238,20 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
                 w2 = p.ce2[g];
                 w3 = p.ce3[g];
             } else {
-                // raw Et at the own cell times E^{n+1} - E^n
-                w1 = A1[g] * (En1[g] - En[g]);
-                w2 = A2[g] * (En1[g + fs3] - En[g + fs3]);
-                w3 = A3[g] * (En1[g + 2 * fs3] - En[g + 2 * fs3]);
+                // raw Et at the own cell, E^{n+1} and E^n (their product is
+                // formed when the plane is computed, after the loads landed)
+                xa1 = A1[g];
+                xa2 = A2[g];
+                xa3 = A3[g];
+                xn1 = En1[g];
+                xn2 = En1[g + fs3];
+                xn3 = En1[g + 2 * fs3];
+                xp1 = En[g];
+                xp2 = En[g + fs3];
+                xp3 = En[g + 2 * fs3];
+                gn1 = gr[g];
+                gn2 = gr[g + p.gstride];
+                gn3 = gr[g + 2 * p.gstride];
             }
         }
     };
@@ -262,7 +273,13 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
                 (&s1y[b][0][0])[tid + u * NT] = f1y[u];
             }
         const float u1 = o1, u2 = o2, u3 = o3;
+        const float g1 = gn1, g2 = gn2, g3 = gn3;
         float v1 = w1, v2 = w2, v3 = w3;
+        if (!REV_H) {
+            v1 = xa1 * (xn1 - xp1);
+            v2 = xa2 * (xn2 - xp2);
+            v3 = xa3 * (xn3 - xp3);
+        }
         const unsigned vi = wi;
         __syncthreads();
         if (k + 1 < k1) issue(k + 1);
@@ -272,7 +289,7 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
             v3 = sCe[(vi >> 16) & 255u];
         }
         if (valid) {
-            const float *cz = p.tz + k * L;
+            const cfloat *cz = uniform_table(p.tz + k * L);
             float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
 #pragma unroll
             for (int m = 0; m < L; ++m) {
@@ -290,9 +307,9 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
                 O2[g] = u2 + v2 * p.scale * c2;
                 O3[g] = u3 + v3 * p.scale * c3;
             } else {
-                gr[g] += v1;
-                gr[g + p.gstride] += v2;
-                gr[g + 2 * p.gstride] += v3;
+                gr[g] = g1 + v1;
+                gr[g + p.gstride] = g2 + v2;
+                gr[g + 2 * p.gstride] = g3 + v3;
                 O1[g] = u1 - p.scale * c1;
                 O2[g] = u2 - p.scale * c2;
                 O3[g] = u3 - p.scale * c3;

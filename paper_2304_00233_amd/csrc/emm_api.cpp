@@ -100,6 +100,7 @@ struct Tune {
     int compact = 0;   // compact dt/eps in the E step
     int tx = 64;       // tile width of the step kernels
     int ry = 1;        // rows per wavefront (2, 4: register-blocked 64-wide tiles)
+    int sorder = 0;    // tile order of the sources (0: fastest, 1: slowest)
 };
 
 struct emm_model {
@@ -288,6 +289,17 @@ int choose_tx(const emm_model *m, int nsrc) {
     return (m->r >= 3 || e32 > e64 + 0.02) ? 32 : 64;
 }
 
+// Tile order of the sources: the option, the autotuner's choice, else
+// source fastest.
+int choose_sorder(const emm_model *m, int nsrc) {
+    if (m->opt.src_order >= 0) return m->opt.src_order;
+    if (m->opt.tile_kz < 0) {
+        auto it = m->tuned.find(nsrc);
+        if (it != m->tuned.end()) return it->second.sorder;
+    }
+    return 0;
+}
+
 // Rows per wavefront of the step kernels: the option, the autotuner's
 // choice, else 1 (one row per wavefront, step_kernel).
 int choose_ry(const emm_model *m, int nsrc) {
@@ -315,6 +327,7 @@ void note_run(emm_model *m, const emm::StepParams &Pe) {
     m->info.tile_kz = Pe.kz;
     m->info.tile_x = Pe.tx;
     m->info.tile_rows = Pe.ry;
+    m->info.src_order = Pe.sorder;
     m->info.nontemporal = Pe.stream;
     m->info.ce_table = Pe.cei != nullptr;
     step_bytes(m, m->info.e_bytes, m->info.h_bytes, Pe.cei != nullptr);
@@ -353,6 +366,7 @@ emm_status emm_default_options(emm_options *o) {
     o->src_group = 0;
     o->tile_x = 0;
     o->tile_rows = 0;
+    o->src_order = -1;
     return EMM_OK;
 }
 
@@ -416,7 +430,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
         opt.airwave < 0 || opt.airwave > 1 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
         opt.fused < 0 || opt.fused > 1 || opt.ce_table < -1 || opt.ce_table > 1 || opt.src_group < -1 || (opt.tile_x != 0 && opt.tile_x != 32 && opt.tile_x != 64) ||
         (opt.tile_rows != 0 && opt.tile_rows != 1 && opt.tile_rows != 2 && opt.tile_rows != 4) ||
-        (opt.tile_rows > 1 && opt.tile_x == 32) ||
+        (opt.tile_rows > 1 && opt.tile_x == 32) || opt.src_order < -1 || opt.src_order > 1 ||
         !(opt.cpml_R > 0.0 && opt.cpml_R < 1.0) || !(opt.cpml_npow >= 0.0) ||
         !(opt.cpml_alpha_max >= 0.0) || !(opt.wavelet_fpeak >= 0.0) || !(opt.dt_override >= 0.0))
         return fail(nullptr, EMM_ERR_ARG, "option out of range");
@@ -928,6 +942,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
     P.kmin = kmin_of(m);
     P.nsrc = nsrc;
     P.nstencil = P.xt * P.yt * P.zc * nsrc;
+    P.sorder = choose_sorder(m, nsrc);
     P.stream = choose_stream(m, fstride, nsrc);
     float *F = (float *)m->fields.p;
     // per-source field arrays are laid out [comp][src][...]: source s at + s * fstride
@@ -1709,6 +1724,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
         Pe.zc = Ph.zc = (nzv + c.kz - 1) / c.kz;
         Pe.nstencil = Ph.nstencil = Pe.xt * Pe.yt * Pe.zc * A.nsrc;
         Pe.stream = Ph.stream = c.stream;
+        Pe.sorder = Ph.sorder = c.sorder;
         Pe.cei = c.compact ? m->cei : nullptr;
         for (int n = 0; n < 2; ++n) {              // warm-up
             emm::launch_e_step(m->r, Pe, n, stream);
@@ -1727,6 +1743,10 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     std::vector<std::pair<float, int>> first;   // (ms, index into tried)
     std::vector<Tune> tried;
     emm_status st;
+    std::vector<int> orders = {0};
+    if (A.nsrc > 1) orders = {0, 1};
+    if (m->opt.src_order >= 0) orders = {m->opt.src_order};
+    for (int so : orders)
     for (auto shape : shapes)
         for (int cp : compacts)
             for (int sh : hints)
@@ -1737,6 +1757,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
                     c.compact = cp;
                     c.tx = shape.first;
                     c.ry = shape.second;
+                    c.sorder = so;
                     float ms = 0.f;
                     if ((st = time_it(c, 6, ms)) != EMM_OK) return st;
                     first.push_back({ms, (int)tried.size()});
@@ -1750,6 +1771,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     pick.compact = A.Pe.cei != nullptr;
     pick.tx = A.Pe.tx;
     pick.ry = A.Pe.ry;
+    pick.sorder = A.Pe.sorder;
     if (!first.empty()) pick = tried[first[0].second];
     for (size_t c = 0; c < std::min<size_t>(4, first.size()); ++c) {
         float ms = 0.f;
@@ -1769,6 +1791,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
         P->zc = (nzv + pick.kz - 1) / pick.kz;
         P->nstencil = P->xt * P->yt * P->zc * A.nsrc;
         P->stream = pick.stream;
+        P->sorder = pick.sorder;
     }
     A.Pe.cei = pick.compact ? m->cei : nullptr;
     return EMM_OK;
@@ -2218,6 +2241,7 @@ emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm
     PE.xt = gt.xt;
     PE.yt = gt.yt;
     PE.zc = A.Pe.zc;
+    PE.sorder = A.Pe.sorder;
     PE.nstencil = PE.xt * PE.yt * PE.zc * nsrc;
     PE.fstride = fstride;
     PE.ce1 = m->ce[0];

@@ -33,6 +33,9 @@ struct StepParams {
     int kmin;                   // first updated z plane (r, or the surface node under air)
     int nsrc;
     int nstencil;               // xt * yt * zc * nsrc
+    int sorder;                 // tile order: 0 = source fastest (the blocks of all sources for
+                                // one spatial tile together), 1 = source slowest (each source's
+                                // tiles contiguous: neighbouring tiles share halos in L2)
     int nrecblk;                // receiver blocks placed first (multiple of 8)
     int stream;                 // 1: nontemporal loads/stores of the arrays touched once per launch
     // fields (source 0; source s at + s * fstride)
@@ -90,6 +93,28 @@ struct LeapParams {
 void launch_leap(int r, const StepParams &pe, const StepParams &ph, const LeapParams &x, int n,
                  hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 int leap_threads();
+
+// Wave-uniform read-only tables (the z rows of the FD tables, the z-CPML
+// coefficients) are read in the constant address space inside the plane
+// loops: scalar loads, counted apart from the vector loads of the next
+// plane's prefetch, so using them does not wait for that prefetch to land.
+typedef __attribute__((address_space(4))) const float cfloat;
+__device__ __forceinline__ const cfloat *uniform_table(const float *p) { return (const cfloat *)p; }
+
+// Source and spatial tile of logical tile t (0 <= t < nstencil, nstencil =
+// tiles * nsrc) in the order `sorder` (see StepParams::sorder); t becomes
+// the spatial tile.
+__device__ __forceinline__ int tile_source(int &t, int nsrc, int nstencil, int sorder) {
+    if (sorder) {
+        const int per = nstencil / nsrc;
+        const int s = t / per;
+        t -= s * per;
+        return s;
+    }
+    const int s = t % nsrc;
+    t /= nsrc;
+    return s;
+}
 
 // Hardware dispatches workgroup w to XCD w % 8; give every XCD one
 // contiguous range of logical tiles.

@@ -40,6 +40,13 @@ constexpr int NT = kTileX * TY;
 
 int block_threads() { return NT; }
 
+// CPML memory-variable update psi <- b psi + a d, with one fixed rounding
+// (b psi fused onto the rounded a d) in every kernel, so that all tile shapes
+// and the fused step give the same bits.
+__device__ __forceinline__ float cpml_mem(float b, float psi, float a, float d) {
+    return __builtin_fmaf(b, psi, a * d);
+}
+
 template <bool ST, typename T>
 __device__ __forceinline__ T ld1(const T *p) {
     if constexpr (ST) return __builtin_nontemporal_load(p);
@@ -142,12 +149,13 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         rec_dft<R>(p, blk, A1, A2, A3, n);
         return;
     }
-    // logical tile: source fastest, then x, y, z chunk, so the blocks of all
-    // sources for one spatial tile run together (on one XCD) and share the
-    // model and table reads through L2
+    // logical tile: source fastest (the blocks of all sources for one
+    // spatial tile run together on one XCD and share the model and table
+    // reads through L2) or slowest (each XCD streams whole sources, and
+    // neighbouring tiles of one source share their halos through L2), then
+    // x, y, z chunk
     int t = xcd_tile(blk - p.nrecblk, p.nstencil);
-    const int s = t % p.nsrc;
-    t /= p.nsrc;
+    const int s = tile_source(t, p.nsrc, p.nstencil, p.sorder);
     const int bxt = t % p.xt;
     t /= p.xt;
     const int byt = t % p.yt;
@@ -269,9 +277,11 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         q2[m] = A2[(unsigned)((k0 - HL + m) * plane + own)];
     }
 
-    // staged registers of the next plane
+    // staged registers of the next plane (fields, dt/eps and the CPML memory
+    // variables of its slab cells)
     float f3[N3], f1[N1], f2 = 0.f, e1n, e2n;
     float un1 = 0.f, un2 = 0.f, un3 = 0.f, cn1 = 0.f, cn2 = 0.f, cn3 = 0.f;
+    float mxn0 = 0.f, mxn1 = 0.f, myn0 = 0.f, myn1 = 0.f, mzn0 = 0.f, mzn1 = 0.f;
     unsigned cin = 0;
     auto issue = [&](int k) {
         const int pk = k * plane;
@@ -284,6 +294,22 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         e1n = A1[ge];
         e2n = A2[ge];
         if (valid) {
+            if (xs) {
+                const unsigned id = (unsigned)((k * p.n2 + j) * nb2 + ix);
+                mxn0 = px0[id];
+                mxn1 = px1[id];
+            }
+            if (ys) {
+                const unsigned id = (unsigned)((k * nb2 + jy) * p.pitch + i);
+                myn0 = py0[id];
+                myn1 = py1[id];
+            }
+            if (k < nb || k > p.n3 - 1 - nb) {
+                const int kz = k < nb ? k : k - (p.n3 - nb2);
+                const unsigned id = (unsigned)((kz * p.n2 + j) * p.pitch + i);
+                mzn0 = pz0[id];
+                mzn1 = pz1[id];
+            }
             const unsigned g = (unsigned)(pk + own);
             un1 = ld1<ST>(&U1[g]);
             un2 = ld1<ST>(&U2[g]);
@@ -315,6 +341,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         sA2[b][ty][tx + HL] = q2[HL];
         sA1[b][ty + HL][tx] = q1[HL];
         const float u1 = un1, u2 = un2, u3 = un3;
+        const float mx0 = mxn0, mx1 = mxn1, my0 = myn0, my1 = myn1, mz0 = mzn0, mz1 = mzn1;
         float ce1 = cn1, ce2 = cn2, ce3 = cn3;
         const unsigned ci = cin;
         __syncthreads();
@@ -326,7 +353,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         }
 
         if (valid) {
-            const float *cz = tz_ + k * L;
+            const cfloat *cz = uniform_table(tz_ + k * L);
             float d2a3 = 0.f, d2a1 = 0.f, d1a3 = 0.f, d1a2 = 0.f, d3a2 = 0.f, d3a1 = 0.f;
 #pragma unroll
             for (int m = 0; m < L; ++m) {
@@ -339,30 +366,30 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
             }
             if (xs) {
                 const unsigned id = (unsigned)((k * p.n2 + j) * nb2 + ix);
-                float v = bx * px0[id] + ax * d1a3;
+                float v = cpml_mem(bx, mx0, ax, d1a3);
                 px0[id] = v;
                 d1a3 += v;
-                v = bx * px1[id] + ax * d1a2;
+                v = cpml_mem(bx, mx1, ax, d1a2);
                 px1[id] = v;
                 d1a2 += v;
             }
             if (ys) {
                 const unsigned id = (unsigned)((k * nb2 + jy) * p.pitch + i);
-                float v = by * py0[id] + ay * d2a3;
+                float v = cpml_mem(by, my0, ay, d2a3);
                 py0[id] = v;
                 d2a3 += v;
-                v = by * py1[id] + ay * d2a1;
+                v = cpml_mem(by, my1, ay, d2a1);
                 py1[id] = v;
                 d2a1 += v;
             }
             if (k < nb || k > p.n3 - 1 - nb) {
                 const int kz = k < nb ? k : k - (p.n3 - nb2);
-                const float az = az_[k], bz = bz_[k];
+                const float az = uniform_table(az_)[k], bz = uniform_table(bz_)[k];
                 const unsigned id = (unsigned)((kz * p.n2 + j) * p.pitch + i);
-                float v = bz * pz0[id] + az * d3a2;
+                float v = cpml_mem(bz, mz0, az, d3a2);
                 pz0[id] = v;
                 d3a2 += v;
-                v = bz * pz1[id] + az * d3a1;
+                v = cpml_mem(bz, mz1, az, d3a1);
                 pz1[id] = v;
                 d3a1 += v;
             }
@@ -430,8 +457,7 @@ __global__ __launch_bounds__(NT) void step_kernel_rb(const StepParams p, int n_a
         return;
     }
     int t = xcd_tile(blk - p.nrecblk, p.nstencil);
-    const int s = t % p.nsrc;
-    t /= p.nsrc;
+    const int s = tile_source(t, p.nsrc, p.nstencil, p.sorder);
     const int bxt = t % p.xt;
     t /= p.xt;
     const int byt = t % p.yt;
@@ -626,7 +652,7 @@ __global__ __launch_bounds__(NT) void step_kernel_rb(const StepParams p, int n_a
             }
         }
         if (ivalid) {
-            const float *cz = tz_ + k * L;
+            const cfloat *cz = uniform_table(tz_ + k * L);
             // the y-tap columns of this thread's rows, read from LDS once
             float c3[NC], c1[NC];
 #pragma unroll
@@ -636,7 +662,7 @@ __global__ __launch_bounds__(NT) void step_kernel_rb(const StepParams p, int n_a
             }
             const bool zs = k < nb || k > p.n3 - 1 - nb;
             const int kz = k < nb ? k : k - (p.n3 - nb2);
-            const float az = zs ? az_[k] : 0.f, bz = zs ? bz_[k] : 0.f;
+            const float az = zs ? uniform_table(az_)[k] : 0.f, bz = zs ? uniform_table(bz_)[k] : 0.f;
 #pragma unroll
             for (int q = 0; q < RY; ++q) {
                 if (!rv[q]) continue;
@@ -653,28 +679,28 @@ __global__ __launch_bounds__(NT) void step_kernel_rb(const StepParams p, int n_a
                 }
                 if (xs) {
                     const unsigned id = (unsigned)((k * p.n2 + j) * nb2 + ix);
-                    float v = bx * px0[id] + ax * d1a3;
+                    float v = cpml_mem(bx, px0[id], ax, d1a3);
                     px0[id] = v;
                     d1a3 += v;
-                    v = bx * px1[id] + ax * d1a2;
+                    v = cpml_mem(bx, px1[id], ax, d1a2);
                     px1[id] = v;
                     d1a2 += v;
                 }
                 if (ys[q]) {
                     const unsigned id = (unsigned)((k * nb2 + jy[q]) * p.pitch + i);
-                    float v = by[q] * py0[id] + ay[q] * d2a3;
+                    float v = cpml_mem(by[q], py0[id], ay[q], d2a3);
                     py0[id] = v;
                     d2a3 += v;
-                    v = by[q] * py1[id] + ay[q] * d2a1;
+                    v = cpml_mem(by[q], py1[id], ay[q], d2a1);
                     py1[id] = v;
                     d2a1 += v;
                 }
                 if (zs) {
                     const unsigned id = (unsigned)((kz * p.n2 + j) * p.pitch + i);
-                    float v = bz * pz0[id] + az * d3a2;
+                    float v = cpml_mem(bz, pz0[id], az, d3a2);
                     pz0[id] = v;
                     d3a2 += v;
-                    v = bz * pz1[id] + az * d3a1;
+                    v = cpml_mem(bz, pz1[id], az, d3a1);
                     pz1[id] = v;
                     d3a1 += v;
                 }
@@ -920,19 +946,19 @@ __global__ __launch_bounds__(kTileX * kLeapRows) void leap_kernel(const StepPara
             const bool wr = own && k >= k0 && k < k1;
             if (xs) {
                 const unsigned id = (unsigned)((k * n2 + j) * nb2 + ix);
-                float v = bxi * ex0[id] + axi * d1a3;
+                float v = cpml_mem(bxi, ex0[id], axi, d1a3);
                 if (wr) qx0[id] = v;
                 d1a3 += v;
-                v = bxi * ex1[id] + axi * d1a2;
+                v = cpml_mem(bxi, ex1[id], axi, d1a2);
                 if (wr) qx1[id] = v;
                 d1a2 += v;
             }
             if (ys) {
                 const unsigned id = (unsigned)((k * nb2 + jy) * pitch + i);
-                float v = byi * ey0[id] + ayi * d2a3;
+                float v = cpml_mem(byi, ey0[id], ayi, d2a3);
                 if (wr) qy0[id] = v;
                 d2a3 += v;
-                v = byi * ey1[id] + ayi * d2a1;
+                v = cpml_mem(byi, ey1[id], ayi, d2a1);
                 if (wr) qy1[id] = v;
                 d2a1 += v;
             }
@@ -940,10 +966,10 @@ __global__ __launch_bounds__(kTileX * kLeapRows) void leap_kernel(const StepPara
                 const int kz = k < nb ? k : k - (n3 - nb2);
                 const float az = pe.azi[k], bz = pe.bzi[k];
                 const unsigned id = (unsigned)((kz * n2 + j) * pitch + i);
-                float v = bz * ez0[id] + az * d3a2;
+                float v = cpml_mem(bz, ez0[id], az, d3a2);
                 if (wr) qz0[id] = v;
                 d3a2 += v;
-                v = bz * ez1[id] + az * d3a1;
+                v = cpml_mem(bz, ez1[id], az, d3a1);
                 if (wr) qz1[id] = v;
                 d3a1 += v;
             }
@@ -994,19 +1020,19 @@ __global__ __launch_bounds__(kTileX * kLeapRows) void leap_kernel(const StepPara
             }
             if (xs) {
                 const unsigned id = (unsigned)((kh * n2 + j) * nb2 + ix);
-                float v = bxh * hx0[id] + axh * d1a3;
+                float v = cpml_mem(bxh, hx0[id], axh, d1a3);
                 hx0[id] = v;
                 d1a3 += v;
-                v = bxh * hx1[id] + axh * d1a2;
+                v = cpml_mem(bxh, hx1[id], axh, d1a2);
                 hx1[id] = v;
                 d1a2 += v;
             }
             if (ys) {
                 const unsigned id = (unsigned)((kh * nb2 + jy) * pitch + i);
-                float v = byh * hy0[id] + ayh * d2a3;
+                float v = cpml_mem(byh, hy0[id], ayh, d2a3);
                 hy0[id] = v;
                 d2a3 += v;
-                v = byh * hy1[id] + ayh * d2a1;
+                v = cpml_mem(byh, hy1[id], ayh, d2a1);
                 hy1[id] = v;
                 d2a1 += v;
             }
@@ -1014,10 +1040,10 @@ __global__ __launch_bounds__(kTileX * kLeapRows) void leap_kernel(const StepPara
                 const int kz = kh < nb ? kh : kh - (n3 - nb2);
                 const float az = ph.azh[kh], bz = ph.bzh[kh];
                 const unsigned id = (unsigned)((kz * n2 + j) * pitch + i);
-                float v = bz * hz0[id] + az * d3a2;
+                float v = cpml_mem(bz, hz0[id], az, d3a2);
                 hz0[id] = v;
                 d3a2 += v;
-                v = bz * hz1[id] + az * d3a1;
+                v = cpml_mem(bz, hz1[id], az, d3a1);
                 hz1[id] = v;
                 d3a1 += v;
             }

@@ -48,7 +48,7 @@ class emm_options(C.Structure):
                 ("checkpoint_inner", C.c_int), ("nontemporal", C.c_int), ("airwave", C.c_int),
                 ("converge_tol", C.c_double), ("converge_every", C.c_int), ("fused", C.c_int),
                 ("ce_table", C.c_int), ("src_group", C.c_int), ("tile_x", C.c_int),
-                ("tile_rows", C.c_int)]
+                ("tile_rows", C.c_int), ("src_order", C.c_int)]
 
 
 class emm_source(C.Structure):
@@ -77,7 +77,7 @@ class emm_info(C.Structure):
                 ("ckpt_outer", C.c_int), ("ckpt_inner", C.c_int), ("ckpt_bytes", C.c_double),
                 ("nontemporal", C.c_int), ("converged", C.c_int), ("fused", C.c_int),
                 ("leap_bytes", C.c_double), ("ce_table", C.c_int), ("src_group", C.c_int),
-                ("tile_x", C.c_int), ("tile_rows", C.c_int)]
+                ("tile_x", C.c_int), ("tile_rows", C.c_int), ("src_order", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -116,6 +116,22 @@ def _load():
 
 
 _lib = _load()
+
+
+def hip_runtimes() -> list:
+    """Paths of the HIP runtime libraries (libamdhip64) mapped into this
+    process.  libemm binds to the first one loaded: a process that imports
+    torch before this module shares torch's runtime with it (one entry here);
+    importing this module first and torch afterwards maps two."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return sorted(paths)
 
 
 class EmmError(RuntimeError):

@@ -62,6 +62,7 @@ def test_default_options(emm):
     assert o.nontemporal == -1 and o.airwave == 0
     assert o.converge_tol == 0.0 and o.converge_every == 100
     assert o.fused == 0 and o.ce_table == -1 and o.src_group == 0 and o.tile_x == 0
+    assert o.tile_rows == 0 and o.src_order == -1
 
 
 def test_status_strings(emm):
@@ -120,6 +121,9 @@ def test_create_validation_errors(emm):
     assert _create_status(emm, xs, rs, ce_table=-2)[0] == -1
     assert _create_status(emm, xs, rs, src_group=-2)[0] == -1
     assert _create_status(emm, xs, rs, tile_x=48)[0] == -1
+    assert _create_status(emm, xs, rs, tile_rows=3)[0] == -1
+    assert _create_status(emm, xs, rs, tile_rows=4, tile_x=32)[0] == -1
+    assert _create_status(emm, xs, rs, src_order=2)[0] == -1
     # the air boundary: option range, uniform x and y, room for the ghost planes
     assert _create_status(emm, xs, rs, airwave=2)[0] == -1
     nu = [x.copy() for x in xs]

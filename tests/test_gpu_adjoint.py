@@ -145,16 +145,17 @@ def test_tile_widths_give_the_same_gradient(emm, rd):
 
 def test_source_groups_give_the_same_gradient(emm):
     """emm_gradient over three sources in groups of one, two (2 + 1) and all
-    at once: the same gradient, misfit and Green's functions bit for bit (the
-    groups add in the order of a single sweep)."""
+    at once (with the blocks of the sources in either order within the
+    launches): the same gradient, misfit and Green's functions bit for bit
+    (the groups add in the order of a single sweep)."""
     w, wo = _case(seed=39, nsrc=3, nt=160)
     G_obs, _ = F.forward(wo)
     out = []
-    for grp in (-1, 1, 2):
-        with emm.Model(w, src_group=grp) as m:
+    for grp, so in ((-1, 0), (1, 0), (2, 0), (-1, 1)):
+        with emm.Model(w, src_group=grp, src_order=so) as m:
             g, G, c = m.gradient(g_obs=G_obs)
             out.append((g, G, c, m.info()["src_group"]))
-    assert [o[3] for o in out] == [3, 1, 2]
+    assert [o[3] for o in out] == [3, 1, 2, 3]
     for g, G, c, _ in out[1:]:
         assert np.array_equal(g, out[0][0]) and np.array_equal(G, out[0][1]) and c == out[0][2]
 

@@ -118,7 +118,11 @@ def test_bitwise_determinism_runs_and_tiles(emm, rd):
 
 def test_batched_equals_single_sources(emm):
     w = configs.small_case(seed=10, nsrc=4, shape=(28, 26, 24), nt=200)
-    Gb, _ = _run(emm, w)
+    Gb, ib = _run(emm, w)
+    # the blocks of the four sources in either order within the launches
+    Gs1, is1 = _run(emm, w, src_order=1)
+    assert (ib["src_order"], is1["src_order"]) == (0, 1)
+    assert np.array_equal(Gb, Gs1)
     for s in range(4):
         Gs, _ = _run(emm, w.with_(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1]))
         assert np.array_equal(Gb[s:s + 1], Gs)
