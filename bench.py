@@ -379,6 +379,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=50, help="oracle steps on all cores")
     ap.add_argument("--cpu-steps-one", type=int, default=6, help="oracle steps on one core")
+    ap.add_argument("--gradient-sample", type=int, default=0, metavar="NT",
+                    help="only run one forward + gradient (cotangent G) of the workload cut to NT "
+                         "steps, for kernel traces of the adjoint, and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy kernel (for scaling FETCH/WRITE_SIZE)")
     ap.add_argument("--stream-reference", action="store_true",
@@ -438,6 +441,18 @@ def main():
         w = w.with_(nt=args.nt)
     nsrc = len(w.sources)
     log(f"[bench] workload {w.name} padded cells {w.padded_cells} sources {nsrc}")
+    if args.gradient_sample:
+        w = w.with_(nt=args.gradient_sample)
+        with emm.Model(w, tile_kz=args.tile_kz, graph_steps=args.graph) as m:
+            G = m.forward()
+            t = time.perf_counter()
+            m.gradient(g_bar=G)
+            dt = time.perf_counter() - t
+            i = m.info()
+        log(f"[bench] gradient sample: {w.name}, {args.gradient_sample} steps, {nsrc} sources, "
+            f"forward + gradient {dt * 1e3:.1f} ms, checkpoints every {i['ckpt_outer']} "
+            f"(inner {i['ckpt_inner']}), sources per sweep {i['src_group']}")
+        return
 
     model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz, fused=args.fused,
                       tile_x=args.tile_x, tile_rows=args.tile_rows, src_order=args.src_order,
@@ -462,9 +477,10 @@ def main():
         f"h_step avg={h_avg_s * 1e6:.2f} us tile_kz={info['tile_kz']} tile_x={info['tile_x']} "
         f"tile_rows={info['tile_rows']} src_order={info['src_order']} nontemporal={info['nontemporal']} "
         f"ce_table={info['ce_table']}")
+    full_nt = json.load(open(LARGE_GOLDEN))["nt"] if large and os.path.exists(LARGE_GOLDEN) else None
     step_desc = (f"one forward of the {nsrc} sources batched, over a window of {nt} time steps "
-                 f"(of the {18800} of a converged run)" if large else
-                 "one full forward modelling (nt time steps)")
+                 + (f"(of the {full_nt} of a full run)" if full_nt else "of a full run")
+                 if large else "one full forward modelling (nt time steps)")
     out = {
         "metric": "FDTD cell-updates/s (Gcell*step/s) + % HBM peak; batched fwd+grad vs plain fwd",
         "value": value, "unit": "Gcell*step/s", "n_gpus": 1, "steps": args.steps,
