@@ -371,6 +371,9 @@ def main():
                     help="nontemporal hints on the arrays a launch touches once (-1: autotuned)")
     ap.add_argument("--src-order", type=int, default=-1, choices=(-1, 0, 1),
                     help="tile order of the sources (-1: autotuned)")
+    ap.add_argument("--air-transform", type=int, default=1, choices=(1, 2, 3),
+                    help="air-boundary ghost-fill transforms (shallow workload): 1 by plane size, "
+                         "2 hipFFT, 3 direct kernels")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed steps (no batched, accuracy, marine, towline legs)")
     ap.add_argument("--multi-model", action="store_true",
@@ -456,6 +459,7 @@ def main():
 
     model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz, fused=args.fused,
                       tile_x=args.tile_x, tile_rows=args.tile_rows, src_order=args.src_order,
+                      **({"airwave": args.air_transform} if w.airwave else {}),
                       nontemporal=args.nontemporal)
     wall, acc, info = timed_forwards(model, args.steps, args.warmup, "main")
     model.close()
@@ -504,6 +508,8 @@ def main():
         "interior_gcell_step_per_s": (len(w.x1) * len(w.x2) * len(w.x3)) * nt * nsrc * args.steps / wall / 1e9,
         "device_loop_ms_per_step": acc["dev_ms"] / args.steps,
         "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"], "tile_rows": info["tile_rows"],
+                   **({"air_transform": ("hipfft", "direct")[info["air_transform"] - 1]}
+                      if info["air_transform"] else {}),
                    "src_order": info["src_order"], "nontemporal": info["nontemporal"],
                    "compact_dt_eps": info["ce_table"], "graph_steps": args.graph},
     }

@@ -96,11 +96,17 @@ typedef struct {
                               yes when the fields and dt/eps exceed 160 MiB [-1] */
     int    airwave;        /* 1: the first z node is the sea (or land) surface with air above it
                               (Section 3.3): no cell above it is updated and the ghost planes the
-                              stencils reach are filled after each half step by 2-D FFTs (H as a
-                              potential field, E harmonic); needs uniform x and y spacing
-                              (EMM_ERR_GRID otherwise); with graph_steps the fills are captured
-                              in the step graphs; emm_gradient and emm_forward_batch refuse it
-                              (EMM_ERR_ARG) [0] */
+                              stencils reach are filled after each half step from 2-D Fourier
+                              transforms of the surface plane (H as a potential field, E
+                              harmonic); needs uniform x and y spacing (EMM_ERR_GRID otherwise);
+                              with graph_steps the fills are captured in the step graphs;
+                              emm_gradient and emm_forward_batch refuse it (EMM_ERR_ARG).
+                              The transforms: 1 = chosen by plane size (the direct kernels while
+                              both padded horizontal axes have at most 512 points, hipFFT above),
+                              2 = hipFFT in FP32, 3 = the direct kernels: three per fill, in FP64
+                              (each axis split once as n = f m and summed directly), accurate
+                              where the surface field spans many orders of magnitude across the
+                              plane; EMM_ERR_DEVICE above 512 points per axis [0] */
     double converge_tol;   /* > 0: stop early (Section 3.5, Section 4.1) once the lowest-frequency
                               DTFT of E1 at the 8 corner nodes of the interior changes, between two
                               checks converge_every steps apart, by at most converge_tol times its
@@ -179,6 +185,8 @@ typedef struct {
     int    tile_x;           /* columns per block of the last forward's stencil kernels */
     int    tile_rows;        /* grid rows per wavefront of the last forward's stencil kernels */
     int    src_order;        /* tile order of the sources in the last forward's launches */
+    int    air_transform;    /* ghost-fill transforms of the last forward: 0 = no air boundary,
+                                1 = hipFFT, 2 = direct kernels */
 } emm_info;
 
 /* Fill *o with the defaults above: the paper's values where it states them

@@ -328,6 +328,7 @@ void note_run(emm_model *m, const emm::StepParams &Pe) {
     m->info.tile_x = Pe.tx;
     m->info.tile_rows = Pe.ry;
     m->info.src_order = Pe.sorder;
+    m->info.air_transform = m->air ? (m->air->direct() ? 2 : 1) : 0;
     m->info.nontemporal = Pe.stream;
     m->info.ce_table = Pe.cei != nullptr;
     step_bytes(m, m->info.e_bytes, m->info.h_bytes, Pe.cei != nullptr);
@@ -427,7 +428,7 @@ emm_status emm_create(const emm_grid *g, const emm_options *o, emm_model **out) 
     if (!(opt.cfl > 0.0) || !std::isfinite(opt.cfl)) return fail(nullptr, EMM_ERR_ARG, "cfl must be > 0");
     if (opt.nt < 0 || opt.dft_mode < 0 || opt.dft_mode > 1 || opt.tile_kz < -1 || opt.checkpoint_every < 0 || opt.graph_steps < 0 ||
         opt.checkpoint_inner < 0 || opt.nontemporal < -1 || opt.nontemporal > 1 ||
-        opt.airwave < 0 || opt.airwave > 1 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
+        opt.airwave < 0 || opt.airwave > 3 || !(opt.converge_tol >= 0.0) || opt.converge_every < 1 ||
         opt.fused < 0 || opt.fused > 1 || opt.ce_table < -1 || opt.ce_table > 1 || opt.src_group < -1 || (opt.tile_x != 0 && opt.tile_x != 32 && opt.tile_x != 64) ||
         (opt.tile_rows != 0 && opt.tile_rows != 1 && opt.tile_rows != 2 && opt.tile_rows != 4) ||
         (opt.tile_rows > 1 && opt.tile_x == 32) || opt.src_order < -1 || opt.src_order > 1 ||
@@ -1048,6 +1049,7 @@ emm_status prepare(emm_model *m, const emm_source *src, int nsrc, const emm_rece
         const std::vector<double> &z = m->axes[2];
         for (int q = 1; q < r; ++q) as.hE.push_back(z[as.ks] - z[as.ks - q]);
         for (int q = 1; q <= r; ++q) as.hH.push_back(z[as.ks] - 0.5 * (z[as.ks - q] + z[as.ks - q + 1]));
+        as.method = m->opt.airwave - 1;
         m->air.reset();
         auto air = std::make_unique<emm::AirBoundary>();
         std::string err;
@@ -1781,6 +1783,7 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
             pick = tried[first[c].second];
         }
     }
+
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_OK(m, hipGetLastError());

@@ -77,7 +77,8 @@ class emm_info(C.Structure):
                 ("ckpt_outer", C.c_int), ("ckpt_inner", C.c_int), ("ckpt_bytes", C.c_double),
                 ("nontemporal", C.c_int), ("converged", C.c_int), ("fused", C.c_int),
                 ("leap_bytes", C.c_double), ("ce_table", C.c_int), ("src_group", C.c_int),
-                ("tile_x", C.c_int), ("tile_rows", C.c_int), ("src_order", C.c_int)]
+                ("tile_x", C.c_int), ("tile_rows", C.c_int), ("src_order", C.c_int),
+                ("air_transform", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

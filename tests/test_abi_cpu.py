@@ -125,7 +125,7 @@ def test_create_validation_errors(emm):
     assert _create_status(emm, xs, rs, tile_rows=4, tile_x=32)[0] == -1
     assert _create_status(emm, xs, rs, src_order=2)[0] == -1
     # the air boundary: option range, uniform x and y, room for the ghost planes
-    assert _create_status(emm, xs, rs, airwave=2)[0] == -1
+    assert _create_status(emm, xs, rs, airwave=4)[0] == -1
     nu = [x.copy() for x in xs]
     nu[0][3] += 1.0
     st, msg = _create_status(emm, nu, rs, airwave=1)
