@@ -125,6 +125,19 @@ def test_air_boundary_graph_replays_are_bitwise_identical(emm, air):
     assert np.array_equal(G0, G1) and np.array_equal(G0, G2)
 
 
+def test_air_direct_fills_with_every_tile_shape_are_bitwise(emm):
+    """The FP64 direct fills with the stencils on 32- and 64-wide tiles,
+    register-blocked tiles, another z chunking and graph replays, two
+    sources in one launch: the same bits."""
+    w = _air_case(58, (41, 29, 23), 2, 6, nsrc=2, nt=200)
+    G0, i0 = emm.forward_workload(w, airwave=3, tile_x=32)
+    assert i0["air_transform"] == 2
+    for kw in (dict(tile_x=64), dict(tile_rows=2), dict(tile_rows=4), dict(tile_x=32, graph_steps=16),
+               dict(tile_x=64, tile_kz=5)):
+        G, _ = emm.forward_workload(w, airwave=3, **kw)
+        assert np.array_equal(G0, G), kw
+
+
 def test_air_boundary_refused_by_gradient_and_batch(emm):
     w = _air_case(54, (21, 20, 19), 2, 4, nt=50)
     with emm.Model(w) as m:
