@@ -247,7 +247,10 @@ def large_batched(emm, w, window, t_batched_fwd):
 def small_towline(emm, nsrc: int = 16):
     """16 x-dipoles every 250 m along x on the 48^3 plain-forward model, all
     in one batched launch per half step, against the plain loop of
-    one-source forwards (a launch-bound grid: 82^3 padded cells)."""
+    one-source forwards (a launch-bound grid: 82^3 padded cells); then the
+    same for forward + gradient (emm_gradient of L = 1/2 sum |G|^2, given by
+    its cotangent G, checkpoints every 50 steps): all sources in one sweep
+    against one source at a time, with the gradients compared."""
     import numpy as np
     from workloads import configs
     w = configs.towline_small(nsrc)
@@ -264,6 +267,23 @@ def small_towline(emm, nsrc: int = 16):
         out["time_steps"] = m.info()["nt"]
     out["bitwise_equal"] = bool(np.array_equal(Gb, np.concatenate(plain, 0)))
     out["speedup"] = out["plain_forward_loop_s"] / out["batched_forward_s"]
+    with emm.Model(w, tile_kz=-1, graph_steps=64, src_group=-1, checkpoint_every=50) as m:
+        m.gradient(g_bar=Gb[:1], sources=w.sources[:1], src_comp=w.src_comp[:1])    # warm
+        m.gradient(g_bar=Gb)
+        t = time.perf_counter()
+        g_sum = None
+        for s in range(nsrc):
+            g, _, _ = m.gradient(g_bar=Gb[s:s + 1], sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1])
+            g_sum = g if g_sum is None else g_sum + g
+        out["plain_forward_gradient_loop_s"] = time.perf_counter() - t
+        t = time.perf_counter()
+        gb, _, _ = m.gradient(g_bar=Gb)
+        out["batched_forward_gradient_s"] = time.perf_counter() - t
+        out["gradient_sources_per_sweep"] = m.info()["src_group"]
+    out["gradient_max_rel_diff"] = float(np.max(np.abs(gb - g_sum)) / np.max(np.abs(gb)))
+    out["fwd_grad_speedup"] = out["plain_forward_gradient_loop_s"] / out["batched_forward_gradient_s"]
+    out["batched_fwd_grad_over_plain_forward_loop"] = (out["batched_forward_gradient_s"] /
+                                                       out["plain_forward_loop_s"])
     return out
 
 
