@@ -18,8 +18,13 @@ What it computes, step by step, in the paper's order (Algorithm 1):
 Pins (tests/test_oracle_*.py): uniform-grid closed-form coefficients,
 polynomial exactness on non-uniform grids, the plane-wave symbol of the
 staggered derivative (appendix on dispersion), the CFL closed form, the
-analytic whole-space electric dipole, the z-domain identity solved by a
-sparse direct solver, reciprocity, omega0- and wavelet-invariance, CPML
-reflection.  Parity of non-homogeneous non-uniform models against a physical
-truth is unpinned (no layered-earth solver available); see oracle.forward.
+analytic whole-space electric dipole (also on a strongly stretched z axis,
+which pins the injection control volume and the padding), the z-domain
+identity solved by a sparse direct solver, reciprocity (also on the marine
+stretched axis with CPML), omega0- and wavelet-invariance, CPML reflection.
+Layered and blocky models are pinned as discrete operators (the z-domain
+identity holds for any model); their discretisation error against the
+continuous layered-earth solution is not measured (no layered-earth solver
+is available), and it is not a parity matter: both implementations
+discretise identically.
 """
