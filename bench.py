@@ -45,14 +45,14 @@ TRAFFIC_KIB = {
     # (workload, kernel, tx, ry, source order, nontemporal, compact, nsrc):
     #     (FETCH_SIZE KiB, WRITE_SIZE KiB); the large grid at 8th order with 8
     #     sources, 58 z planes per block (profiles/step_kernel_large_marine_*)
-    ("large_marine_400x400x200", "e_step", 32, 1, 1, 0, 1, 8): (6547920.6, 4451655.2),
-    ("large_marine_400x400x200", "h_step", 32, 1, 1, 0, 1, 8): (5861969.3, 4450456.0),
-    ("large_marine_400x400x200", "e_step", 64, 1, 1, 0, 1, 8): (6789607.5, 4450503.2),
-    ("large_marine_400x400x200", "h_step", 64, 1, 1, 0, 1, 8): (6024722.6, 4444159.0),
-    ("large_marine_400x400x200", "e_step", 32, 1, 1, 1, 1, 8): (5879356.1, 4445875.8),
-    ("large_marine_400x400x200", "h_step", 32, 1, 1, 1, 1, 8): (5231072.4, 4445578.2),
-    ("large_marine_400x400x200", "e_step", 64, 1, 1, 1, 1, 8): (5873905.4, 4428338.8),
-    ("large_marine_400x400x200", "h_step", 64, 1, 1, 1, 1, 8): (5221831.9, 4426978.2),
+    ("large_marine_400x400x200", "e_step", 32, 1, 1, 0, 1, 8): (6401647.6, 4453677.2),
+    ("large_marine_400x400x200", "h_step", 32, 1, 1, 0, 1, 8): (5792745.6, 4453299.9),
+    ("large_marine_400x400x200", "e_step", 64, 1, 1, 0, 1, 8): (6574432.7, 4450545.0),
+    ("large_marine_400x400x200", "h_step", 64, 1, 1, 0, 1, 8): (5874936.8, 4454413.7),
+    ("large_marine_400x400x200", "e_step", 32, 1, 1, 1, 1, 8): (5845896.3, 4449371.8),
+    ("large_marine_400x400x200", "h_step", 32, 1, 1, 1, 1, 8): (5187237.2, 4451036.2),
+    ("large_marine_400x400x200", "e_step", 64, 1, 1, 1, 1, 8): (5762863.4, 4433150.8),
+    ("large_marine_400x400x200", "h_step", 64, 1, 1, 1, 1, 8): (5067565.9, 4436068.8),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 

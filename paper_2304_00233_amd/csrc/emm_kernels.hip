@@ -40,6 +40,13 @@ constexpr int NT = kTileX * TY;
 
 int block_threads() { return NT; }
 
+// Planes of loads in flight per thread in step_kernel's plane loop: two at
+// 8th order (E/H steps 3-4 % faster on the large grid, 8 sources or one,
+// despite 149-155 registers and 3 waves per SIMD), one below (a second set
+// costs the 2nd-order kernels a wave per SIMD and 24 % on the marine grid).
+template <int R>
+constexpr int prefetch_planes() { return R >= 4 ? 2 : 1; }
+
 // CPML memory-variable update psi <- b psi + a d, with one fixed rounding
 // (b psi fused onto the rounded a d) in every kernel, so that all tile shapes
 // and the fused step give the same bits.
@@ -123,7 +130,7 @@ __device__ void rec_dft(const StepParams &p, int blk, const float *F0,
 // CI (E step only): dt/eps comes from the compact form, one index word per
 // cell (4 bytes instead of 12) into a table of the model's distinct values,
 // held in LDS.  TX: tile width (TX x NT/TX columns per block).
-template <int R, bool HS, bool ST, bool CI, int TX>
+template <int R, bool HS, bool ST, bool CI, int TX, int PF = prefetch_planes<R>()>
 __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg) {
     const int n = (p.step_base ? *p.step_base : 0) + n_arg;
     constexpr int L = 2 * R;
@@ -277,13 +284,22 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         q2[m] = A2[(unsigned)((k0 - HL + m) * plane + own)];
     }
 
-    // staged registers of the next plane (fields, dt/eps and the CPML memory
-    // variables of its slab cells)
-    float f3[N3], f1[N1], f2 = 0.f, e1n, e2n;
-    float un1 = 0.f, un2 = 0.f, un3 = 0.f, cn1 = 0.f, cn2 = 0.f, cn3 = 0.f;
-    float mxn0 = 0.f, mxn1 = 0.f, myn0 = 0.f, myn1 = 0.f, mzn0 = 0.f, mzn1 = 0.f;
-    unsigned cin = 0;
-    auto issue = [&](int k) {
+    // staged registers of a plane in flight (fields, dt/eps and the CPML
+    // memory variables of its slab cells); PF sets, so that the loads of PF
+    // planes are in flight while one is computed
+    struct Stage {
+        float f3[N3], f1[N1], f2, e1n, e2n;
+        float un1, un2, un3, cn1, cn2, cn3;
+        float mxn0, mxn1, myn0, myn1, mzn0, mzn1;
+        unsigned cin;
+    };
+    auto issue = [&](Stage &S, int k) {
+        float(&f3)[N3] = S.f3;
+        float(&f1)[N1] = S.f1;
+        float &f2 = S.f2, &e1n = S.e1n, &e2n = S.e2n, &un1 = S.un1, &un2 = S.un2, &un3 = S.un3;
+        float &cn1 = S.cn1, &cn2 = S.cn2, &cn3 = S.cn3, &mxn0 = S.mxn0, &mxn1 = S.mxn1;
+        float &myn0 = S.myn0, &myn1 = S.myn1, &mzn0 = S.mzn0, &mzn1 = S.mzn1;
+        unsigned &cin = S.cin;
         const int pk = k * plane;
 #pragma unroll
         for (int u = 0; u < N3; ++u) f3[u] = o3[u] >= 0 ? A3[(unsigned)(pk + o3[u])] : 0.f;
@@ -323,12 +339,13 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
             }
         }
     };
-    issue(k0);
-
-    for (int k = k0; k < k1; ++k) {
+    auto step = [&](Stage &S, int k) {
         const int b = (k - k0) & 1;
-        q1[L - 1] = e1n;
-        q2[L - 1] = e2n;
+        const float(&f3)[N3] = S.f3;
+        const float(&f1)[N1] = S.f1;
+        const float f2 = S.f2;
+        q1[L - 1] = S.e1n;
+        q2[L - 1] = S.e2n;
         float *s3 = &sA3[b][0][0];
 #pragma unroll
         for (int u = 0; u < N3; ++u)
@@ -340,12 +357,12 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
         if (l2 >= 0) (&sA2[b][0][0])[l2] = o2 >= 0 ? f2 : 0.f;
         sA2[b][ty][tx + HL] = q2[HL];
         sA1[b][ty + HL][tx] = q1[HL];
-        const float u1 = un1, u2 = un2, u3 = un3;
-        const float mx0 = mxn0, mx1 = mxn1, my0 = myn0, my1 = myn1, mz0 = mzn0, mz1 = mzn1;
-        float ce1 = cn1, ce2 = cn2, ce3 = cn3;
-        const unsigned ci = cin;
+        const float u1 = S.un1, u2 = S.un2, u3 = S.un3;
+        const float mx0 = S.mxn0, mx1 = S.mxn1, my0 = S.myn0, my1 = S.myn1, mz0 = S.mzn0, mz1 = S.mzn1;
+        float ce1 = S.cn1, ce2 = S.cn2, ce3 = S.cn3;
+        const unsigned ci = S.cin;
         __syncthreads();
-        if (k + 1 < k1) issue(k + 1);
+        if (k + PF < k1) issue(S, k + PF);
         if (CI) {
             ce1 = sCe[ci & 255u];
             ce2 = sCe[(ci >> 8) & 255u];
@@ -416,6 +433,19 @@ __global__ __launch_bounds__(NT) void step_kernel(const StepParams p, int n_arg)
             q1[m] = q1[m + 1];
             q2[m] = q2[m + 1];
         }
+    };
+    Stage SA = {}, SB = {};
+    issue(SA, k0);
+    int k = k0;
+    if (PF == 2) {
+        if (k0 + 1 < k1) issue(SB, k0 + 1);
+        for (; k + 1 < k1; k += 2) {
+            step(SA, k);
+            step(SB, k + 1);
+        }
+        if (k < k1) step(SA, k);
+    } else {
+        for (; k < k1; ++k) step(SA, k);
     }
 }
 
