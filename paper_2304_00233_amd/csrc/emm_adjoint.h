@@ -61,6 +61,12 @@ struct InjectParams {
 void launch_adj_filter(bool rev_h, const AdjParams &p, hipStream_t st);
 void launch_adj_inject(const InjectParams &p, int n, hipStream_t st);
 void launch_adj_flush(const AdjParams &p, hipStream_t st);
+// the gradient per source and padded cell [s][c][cells] summed over sources
+// and folded onto the input cells (negated: d/dlog sigma = -d/dlog(dt/eps)),
+// into out[c][nd2][nd1][nd0], added to it when accumulate
+void launch_adj_fold(const double *grad, double *out, int nsrc, long long fstride, long long plane, int pitch,
+                     int n1, int n2, int n3, int r, int nbe, int nd0, int nd1, int nd2, bool accumulate,
+                     hipStream_t st);
 void launch_adj_tile(int r, bool rev_h, const AdjParams &p, hipStream_t st);
 
 }  // namespace emm

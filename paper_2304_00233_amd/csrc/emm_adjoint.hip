@@ -114,7 +114,8 @@ __global__ __launch_bounds__(AT) void adj_filter(const AdjParams p) {
 // slab array T inside the slab of its axis, the field elsewhere, zero off
 // the update set on that axis).  CI (reverse of the H update only): dt/eps
 // from the compact form, the table in LDS.
-template <int R, bool REV_H, bool CI, int TX>
+// planes of loads in flight per thread: two at 8th order, as in step_kernel
+template <int R, bool REV_H, bool CI, int TX, int PF = (R >= 4 ? 2 : 1)>
 __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
     constexpr int NT = kTileX * kTileY, TY = NT / TX;
     static_assert(TX * TY == NT && (TX & (TX - 1)) == 0, "tile of NT threads, power-of-two width");
@@ -207,12 +208,24 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
     const float *En1 = REV_H ? nullptr : p.E_next + fo, *En = REV_H ? nullptr : p.E_prev + fo;
     float *gr = REV_H ? nullptr : p.grad32 + (long long)s * 3 * p.gstride;
 
-    float f3x[NX], f2x[NX], f3y[NY], f1y[NY], e1n = 0.f, e2n = 0.f;
-    float o1 = 0.f, o2 = 0.f, o3 = 0.f, w1 = 0.f, w2 = 0.f, w3 = 0.f;
-    float gn1 = 0.f, gn2 = 0.f, gn3 = 0.f;           // FP32 gradient partial sums (reverse of the E update)
-    float xa1 = 0.f, xa2 = 0.f, xa3 = 0.f, xn1 = 0.f, xn2 = 0.f, xn3 = 0.f, xp1 = 0.f, xp2 = 0.f, xp3 = 0.f;
-    unsigned wi = 0;
-    auto issue = [&](int k) {
+    // staged registers of a plane in flight; PF sets, so that the loads of PF
+    // planes are in flight while one is computed
+    struct Stage {
+        float f3x[NX], f2x[NX], f3y[NY], f1y[NY], e1n, e2n;
+        float o1, o2, o3, w1, w2, w3;
+        float gn1, gn2, gn3;                  // FP32 gradient partial sums (reverse of the E update)
+        float xa1, xa2, xa3, xn1, xn2, xn3, xp1, xp2, xp3;
+        unsigned wi;
+    };
+    auto issue = [&](Stage &S, int k) {
+        float(&f3x)[NX] = S.f3x;
+        float(&f2x)[NX] = S.f2x;
+        float(&f3y)[NY] = S.f3y;
+        float(&f1y)[NY] = S.f1y;
+        float &e1n = S.e1n, &e2n = S.e2n, &o1 = S.o1, &o2 = S.o2, &o3 = S.o3, &w1 = S.w1, &w2 = S.w2, &w3 = S.w3;
+        float &gn1 = S.gn1, &gn2 = S.gn2, &gn3 = S.gn3, &xa1 = S.xa1, &xa2 = S.xa2, &xa3 = S.xa3;
+        float &xn1 = S.xn1, &xn2 = S.xn2, &xn3 = S.xn3, &xp1 = S.xp1, &xp2 = S.xp2, &xp3 = S.xp3;
+        unsigned &wi = S.wi;
         const int pk = k * plane;
 #pragma unroll
         for (int u = 0; u < NX; ++u) {
@@ -255,11 +268,14 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
             }
         }
     };
-    issue(k0);
-    for (int k = k0; k < k1; ++k) {
+    auto step = [&](Stage &S, int k) {
         const int b = (k - k0) & 1;
-        q1[L - 1] = e1n;
-        q2[L - 1] = e2n;
+        const float(&f3x)[NX] = S.f3x;
+        const float(&f2x)[NX] = S.f2x;
+        const float(&f3y)[NY] = S.f3y;
+        const float(&f1y)[NY] = S.f1y;
+        q1[L - 1] = S.e1n;
+        q2[L - 1] = S.e2n;
 #pragma unroll
         for (int u = 0; u < NX; ++u)
             if (u < NX - 1 || tid + u * NT < TY * W) {
@@ -272,17 +288,17 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
                 (&s3y[b][0][0])[tid + u * NT] = f3y[u];
                 (&s1y[b][0][0])[tid + u * NT] = f1y[u];
             }
-        const float u1 = o1, u2 = o2, u3 = o3;
-        const float g1 = gn1, g2 = gn2, g3 = gn3;
-        float v1 = w1, v2 = w2, v3 = w3;
+        const float u1 = S.o1, u2 = S.o2, u3 = S.o3;
+        const float g1 = S.gn1, g2 = S.gn2, g3 = S.gn3;
+        float v1 = S.w1, v2 = S.w2, v3 = S.w3;
         if (!REV_H) {
-            v1 = xa1 * (xn1 - xp1);
-            v2 = xa2 * (xn2 - xp2);
-            v3 = xa3 * (xn3 - xp3);
+            v1 = S.xa1 * (S.xn1 - S.xp1);
+            v2 = S.xa2 * (S.xn2 - S.xp2);
+            v3 = S.xa3 * (S.xn3 - S.xp3);
         }
-        const unsigned vi = wi;
+        const unsigned vi = S.wi;
         __syncthreads();
-        if (k + 1 < k1) issue(k + 1);
+        if (k + PF < k1) issue(S, k + PF);
         if (CI) {
             v1 = sCe[vi & 255u];
             v2 = sCe[(vi >> 8) & 255u];
@@ -320,6 +336,19 @@ __global__ __launch_bounds__(kTileX * kTileY) void adj_tile(const AdjParams p) {
             q1[m] = q1[m + 1];
             q2[m] = q2[m + 1];
         }
+    };
+    Stage SA = {}, SB = {};
+    issue(SA, k0);
+    int k = k0;
+    if (PF == 2) {
+        if (k0 + 1 < k1) issue(SB, k0 + 1);
+        for (; k + 1 < k1; k += 2) {
+            step(SA, k);
+            step(SB, k + 1);
+        }
+        if (k < k1) step(SA, k);
+    } else {
+        for (; k < k1; ++k) step(SA, k);
     }
 }
 
@@ -362,6 +391,44 @@ __global__ __launch_bounds__(AT) void adj_flush(const AdjParams p) {
         p.grad[t] += (double)v / (double)ce[g];
         p.grad32[t] = 0.f;
     }
+}
+
+// out[((c nd2 + kk) nd1 + jj) nd0 + ii] = (accumulate ? out : 0) - sum over
+// sources s, then the padded cells (k, j, i) of the update set that fold
+// onto input cell (ii, jj, kk) (the padding layers onto the edge cells), in
+// increasing k, j, i, of grad[s][c][k][j][i]: the sum over sources and the
+// fold of the model padding, in a fixed order per output.
+__global__ __launch_bounds__(AT) void adj_fold(const double *grad, double *out, int nsrc, long long fstride,
+                                               long long plane, int pitch, int n1, int n2, int n3, int r, int nbe,
+                                               int nd0, int nd1, int nd2, int accumulate) {
+    const long long t = (long long)blockIdx.x * AT + threadIdx.x;
+    const long long per = (long long)nd0 * nd1 * nd2;
+    if (t >= 3 * per) return;
+    const int c = (int)(t / per);
+    long long u = t - (long long)c * per;
+    const int kk = (int)(u / ((long long)nd0 * nd1));
+    u -= (long long)kk * nd0 * nd1;
+    const int jj = (int)(u / nd0), ii = (int)(u - (long long)jj * nd0);
+    const int i0 = ii == 0 ? r : ii + nbe, i1 = ii == nd0 - 1 ? n1 - 1 - r : ii + nbe;
+    const int j0 = jj == 0 ? r : jj + nbe, j1 = jj == nd1 - 1 ? n2 - 1 - r : jj + nbe;
+    const int k0 = kk == 0 ? r : kk + nbe, k1 = kk == nd2 - 1 ? n3 - 1 - r : kk + nbe;
+    double acc = accumulate ? out[t] : 0.0;
+    for (int s = 0; s < nsrc; ++s) {
+        const double *g = grad + ((long long)s * 3 + c) * fstride;
+        for (int k = k0; k <= k1; ++k)
+            for (int j = j0; j <= j1; ++j)
+                for (int i = i0; i <= i1; ++i) acc -= g[(long long)k * plane + (long long)j * pitch + i];
+    }
+    out[t] = acc;
+}
+
+void launch_adj_fold(const double *grad, double *out, int nsrc, long long fstride, long long plane, int pitch,
+                     int n1, int n2, int n3, int r, int nbe, int nd0, int nd1, int nd2, bool accumulate,
+                     hipStream_t st) {
+    const long long total = 3LL * nd0 * nd1 * nd2;
+    const dim3 grid((unsigned)((total + AT - 1) / AT)), block(AT);
+    hipLaunchKernelGGL(adj_fold, grid, block, 0, st, grad, out, nsrc, fstride, plane, pitch, n1, n2, n3, r, nbe, nd0,
+                       nd1, nd2, accumulate ? 1 : 0);
 }
 
 void launch_adj_flush(const AdjParams &p, hipStream_t st) {

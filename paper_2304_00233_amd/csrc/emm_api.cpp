@@ -130,6 +130,7 @@ struct emm_model {
     // adjoint: Et|Hb fields, Q (12 slab arrays), T (6), E snapshots, per-source
     // gradients, transposed tables, injection lists and coefficients
     DevBuf adjf, adjq, adjt, snaps, grad, grad32, tabT, inj, injA, adjcpml;
+    DevBuf gsum;                                    // dL/dlog sigma on the input cells, summed over sources
     Acq acq;
     std::map<int, Tune> tuned;                      // autotuned launch choices per source count
     std::unique_ptr<emm::AirBoundary> air;          // ghost planes above the surface (airwave)
@@ -1963,18 +1964,19 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
 emm_status ckpt_budget(emm_model *m, int g, size_t &bud) {
     const long long fs = (long long)m->pitch * m->np[1] * m->np[2];
     const size_t slab_src = (state_floats(m) - 6 * fs) / 2;     // 6 slab arrays per source
-    const size_t need[7] = {(size_t)6 * g * fs * sizeof(float),
+    const size_t need[8] = {(size_t)6 * g * fs * sizeof(float),
                             std::max<size_t>(1, 2 * g * slab_src) * sizeof(float),
                             std::max<size_t>(1, g * slab_src) * sizeof(float),
                             (size_t)3 * g * fs * sizeof(double),
                             (size_t)3 * g * fs * sizeof(float),
                             (size_t)6 * g * fs * sizeof(float),
-                            std::max<size_t>(1, 2 * g * slab_src) * sizeof(float)};
-    const DevBuf *have[7] = {&m->adjf, &m->adjq, &m->adjt, &m->grad, &m->grad32, &m->fields, &m->psi};
+                            std::max<size_t>(1, 2 * g * slab_src) * sizeof(float),
+                            (size_t)3 * m->n[0] * m->n[1] * m->n[2] * sizeof(double)};
+    const DevBuf *have[8] = {&m->adjf, &m->adjq, &m->adjt, &m->grad, &m->grad32, &m->fields, &m->psi, &m->gsum};
     size_t fr = 0, tot = 0;
     HIP_OK(m, hipMemGetInfo(&fr, &tot));
     long long budget = (long long)fr + (long long)(m->ckpts.bytes + m->ickpts.bytes + m->snaps.bytes);
-    for (int b = 0; b < 7; ++b) budget -= (long long)(need[b] > have[b]->bytes ? need[b] - have[b]->bytes : 0);
+    for (int b = 0; b < 8; ++b) budget -= (long long)(need[b] > have[b]->bytes ? need[b] - have[b]->bytes : 0);
     budget -= (long long)(tot / 50) + (256LL << 20);
     bud = budget > 0 ? (size_t)budget : 0;
     return EMM_OK;
@@ -2354,26 +2356,17 @@ emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm
                 return st;
     }
     // sum over sources, drop the pitch padding, fold the model padding back onto
-    // the input cells, and change sign: d/d log sigma = -d/d log(dt/eps)
-    std::vector<double> g((size_t)3 * nsrc * fstride);
-    HIP_OK(m, hipMemcpyAsync(g.data(), m->grad.p, g.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
-    HIP_OK(m, hipStreamSynchronize(stream));
+    // the input cells, and change sign: d/d log sigma = -d/d log(dt/eps); on
+    // the device (the running sum over source groups stays there), then one
+    // copy of the input-cell gradient to the caller
     const int nd0 = m->n[0], nd1 = m->n[1], nd2 = m->n[2];
-    if (!accumulate) std::fill(grad, grad + (size_t)3 * nd0 * nd1 * nd2, 0.0);
-    for (int c = 0; c < 3; ++c)
-        for (int s = 0; s < nsrc; ++s)
-            for (int k = r; k <= n3 - 1 - r; ++k) {
-                const int kk = std::min(std::max(k - m->nbe, 0), nd2 - 1);
-                for (int j = r; j <= n2 - 1 - r; ++j) {
-                    const int jj = std::min(std::max(j - m->nbe, 0), nd1 - 1);
-                    const double *row = &g[((size_t)s * 3 + c) * fstride + (size_t)k * plane + (size_t)j * m->pitch];
-                    double *out = grad + (((size_t)c * nd2 + kk) * nd1 + jj) * nd0;
-                    for (int i = r; i <= n1 - 1 - r; ++i) {
-                        const int ii = std::min(std::max(i - m->nbe, 0), nd0 - 1);
-                        out[ii] -= row[i];
-                    }
-                }
-            }
+    const size_t nout = (size_t)3 * nd0 * nd1 * nd2;
+    if ((st = ensure(m, m->gsum, nout * sizeof(double))) != EMM_OK) return st;
+    emm::launch_adj_fold((const double *)m->grad.p, (double *)m->gsum.p, nsrc, fstride, plane, m->pitch, n1, n2,
+                         n3, r, m->nbe, nd0, nd1, nd2, accumulate, stream);
+    HIP_OK(m, hipGetLastError());
+    HIP_OK(m, hipMemcpyAsync(grad, m->gsum.p, nout * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_OK(m, hipStreamSynchronize(stream));
     return EMM_OK;
 }
 
