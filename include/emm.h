@@ -322,9 +322,12 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
  *   c = 0, 1, 2 for the conductivities behind rho11, rho22, rho33,
  * summed over sources (3*n1*n2*n3 doubles, caller-owned), with dt, the step
  * count and the CPML profile held fixed (they depend on the largest
- * resistivities).  green (may be NULL) receives G.  If the previous
- * emm_forward on this model ran with checkpoint_every > 0 and the same
- * acquisition, its checkpoints are reused; otherwise the forward is run here.
+ * resistivities).  green (may be NULL) receives G.  If the previous call on
+ * this model left checkpoints of the same acquisition (an emm_forward with
+ * checkpoint_every > 0, or an emm_gradient, whose own forward stores them),
+ * they are reused and only the reverse sweep runs; otherwise the forward is
+ * run here.  The sum over sources and the fold of the padding onto the
+ * input cells run on the device.
  * This is the gradient that CSEM inversion needs (the paper's stated
  * horizon, Section 9).  Errors: as emm_forward, plus ARG. */
 emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc,
