@@ -131,6 +131,21 @@ struct emm_model {
     // gradients, transposed tables, injection lists and coefficients
     DevBuf adjf, adjq, adjt, snaps, grad, grad32, tabT, inj, injA, adjcpml;
     DevBuf gsum;                                    // dL/dlog sigma on the input cells, summed over sources
+    // receiver injection lists of the last emm_gradient (CSR over target
+    // cells, in m->inj), kept while the acquisition's receiver items, the
+    // source count and the layout stay the same: building them sorts
+    // (2r)^3 entries per item (~5 M for 8 sources x 400 receivers x 3
+    // channels at 8th order, ~0.4 s)
+    struct InjCache {
+        bool valid = false;
+        std::vector<int> items_e, items_h;
+        std::vector<float> w_e, w_h;
+        int nsrc = 0;
+        long long fstride = 0;
+        void *base = nullptr;
+        int ncells[2] = {0, 0};
+        const void *ptr[12] = {};
+    } injc;
     Acq acq;
     std::map<int, Tune> tuned;                      // autotuned launch choices per source count
     std::unique_ptr<emm::AirBoundary> air;          // ghost planes above the surface (airwave)
@@ -2123,77 +2138,108 @@ emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm
     HIP_OK(m, hipMemsetAsync(m->grad32.p, 0, (size_t)3 * nsrc * fstride * sizeof(float), stream));
 
     // receiver injection lists (CSR over target cells, fixed order): E channels
-    // target Et (scaled by dt/eps), H channels target Hb
-    std::vector<int> rowE, rowH, itE, itH, compE, compH;
-    std::vector<float> wE, wH;
-    std::vector<long long> cellE, cellH, mcE, mcH;
-    for (int kind = 0; kind < 2; ++kind) {            // 0: E channels (items_hstep), 1: H channels
-        const std::vector<int> &items = kind == 0 ? A.items_hstep : A.items_estep;
-        const std::vector<float> &wts = kind == 0 ? A.w_hstep : A.w_estep;
-        std::vector<std::pair<long long, std::pair<int, float>>> ent;  // (target key, (slot, weight))
-        const int nit = (int)items.size() / 6;
-        for (int q = 0; q < nit; ++q) {
-            const int *inf = &items[6 * q];
-            const int s = inf[0], f = inf[1], bx = inf[2], by = inf[3], bz = inf[4], slot = inf[5];
-            const float *w = &wts[(size_t)3 * L * q];
-            for (int c3 = 0; c3 < L; ++c3)
-                for (int b = 0; b < L; ++b)
-                    for (int a = 0; a < L; ++a) {
-                        const long long mc = (long long)(bz + c3) * plane + (long long)(by + b) * m->pitch + bx + a;
-                        const long long key = ((long long)f * nsrc + s) * fstride + mc;
-                        ent.push_back({key, {slot, w[a] * w[L + b] * w[2 * L + c3]}});
-                    }
-        }
-        std::stable_sort(ent.begin(), ent.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
-        std::vector<int> &row = kind == 0 ? rowE : rowH;
-        std::vector<int> &it = kind == 0 ? itE : itH;
-        std::vector<int> &cp_ = kind == 0 ? compE : compH;
-        std::vector<float> &ww = kind == 0 ? wE : wH;
-        std::vector<long long> &cell = kind == 0 ? cellE : cellH;
-        std::vector<long long> &mcell = kind == 0 ? mcE : mcH;
-        for (size_t e = 0; e < ent.size(); ++e) {
-            if (e == 0 || ent[e].first != ent[e - 1].first) {
-                row.push_back((int)it.size());
-                const long long key = ent[e].first;
-                const int f = (int)(key / ((long long)nsrc * fstride));
-                cp_.push_back(f);
-                cell.push_back(key - (long long)f * nsrc * fstride);    // within the component array
-                mcell.push_back(key % fstride);
-            }
-            it.push_back(ent[e].second.first);
-            ww.push_back(ent[e].second.second);
-        }
-        row.push_back((int)it.size());
-    }
-    // one device buffer for both lists
-    auto bytes_of = [](const auto &v) { return v.size() * sizeof(v[0]); };
-    const size_t inj_bytes = bytes_of(rowE) + bytes_of(rowH) + bytes_of(itE) + bytes_of(itH) + bytes_of(wE) +
-                             bytes_of(wH) + bytes_of(cellE) + bytes_of(cellH) + bytes_of(mcE) + bytes_of(mcH) +
-                             bytes_of(compE) + bytes_of(compH) + 16 * 12;
-    if ((st = ensure(m, m->inj, inj_bytes)) != EMM_OK) return st;
+    // target Et (scaled by dt/eps), H channels target Hb; rebuilt only when the
+    // receiver items change
+    emm_model::InjCache &ic = m->injc;
+    const bool inj_cached = ic.valid && ic.nsrc == nsrc && ic.fstride == fstride && ic.base == m->inj.p &&
+                            ic.items_e == A.items_hstep && ic.items_h == A.items_estep && ic.w_e == A.w_hstep &&
+                            ic.w_h == A.w_estep;
     if ((st = ensure(m, m->injA, nd * sizeof(double2))) != EMM_OK) return st;
     HIP_OK(m, hipMemcpy(m->injA.p, Acoef.data(), nd * sizeof(double2), hipMemcpyHostToDevice));
-    char *ip = (char *)m->inj.p;
-    size_t io = 0;
-    auto up = [&](const auto &v) -> const void * {
-        io = (io + 15) / 16 * 16;
-        void *d = ip + io;
-        if (!v.empty()) (void)hipMemcpy(d, v.data(), bytes_of(v), hipMemcpyHostToDevice);
-        io += bytes_of(v);
-        return d;
-    };
+    if (!inj_cached) {
+        ic.valid = false;
+        std::vector<int> rowE, rowH, itE, itH, compE, compH;
+        std::vector<float> wE, wH;
+        std::vector<long long> cellE, cellH, mcE, mcH;
+        for (int kind = 0; kind < 2; ++kind) {            // 0: E channels (items_hstep), 1: H channels
+            const std::vector<int> &items = kind == 0 ? A.items_hstep : A.items_estep;
+            const std::vector<float> &wts = kind == 0 ? A.w_hstep : A.w_estep;
+            std::vector<std::pair<long long, std::pair<int, float>>> ent;  // (target key, (slot, weight))
+            const int nit = (int)items.size() / 6;
+            for (int q = 0; q < nit; ++q) {
+                const int *inf = &items[6 * q];
+                const int s = inf[0], f = inf[1], bx = inf[2], by = inf[3], bz = inf[4], slot = inf[5];
+                const float *w = &wts[(size_t)3 * L * q];
+                for (int c3 = 0; c3 < L; ++c3)
+                    for (int b = 0; b < L; ++b)
+                        for (int a = 0; a < L; ++a) {
+                            const long long mc = (long long)(bz + c3) * plane + (long long)(by + b) * m->pitch + bx + a;
+                            const long long key = ((long long)f * nsrc + s) * fstride + mc;
+                            ent.push_back({key, {slot, w[a] * w[L + b] * w[2 * L + c3]}});
+                        }
+            }
+            std::stable_sort(ent.begin(), ent.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+            std::vector<int> &row = kind == 0 ? rowE : rowH;
+            std::vector<int> &it = kind == 0 ? itE : itH;
+            std::vector<int> &cp_ = kind == 0 ? compE : compH;
+            std::vector<float> &ww = kind == 0 ? wE : wH;
+            std::vector<long long> &cell = kind == 0 ? cellE : cellH;
+            std::vector<long long> &mcell = kind == 0 ? mcE : mcH;
+            for (size_t e = 0; e < ent.size(); ++e) {
+                if (e == 0 || ent[e].first != ent[e - 1].first) {
+                    row.push_back((int)it.size());
+                    const long long key = ent[e].first;
+                    const int f = (int)(key / ((long long)nsrc * fstride));
+                    cp_.push_back(f);
+                    cell.push_back(key - (long long)f * nsrc * fstride);    // within the component array
+                    mcell.push_back(key % fstride);
+                }
+                it.push_back(ent[e].second.first);
+                ww.push_back(ent[e].second.second);
+            }
+            row.push_back((int)it.size());
+        }
+        // one device buffer for both lists
+        auto bytes_of = [](const auto &v) { return v.size() * sizeof(v[0]); };
+        const size_t inj_bytes = bytes_of(rowE) + bytes_of(rowH) + bytes_of(itE) + bytes_of(itH) + bytes_of(wE) +
+                                 bytes_of(wH) + bytes_of(cellE) + bytes_of(cellH) + bytes_of(mcE) + bytes_of(mcH) +
+                                 bytes_of(compE) + bytes_of(compH) + 16 * 12;
+        if ((st = ensure(m, m->inj, inj_bytes)) != EMM_OK) return st;
+        char *ip = (char *)m->inj.p;
+        size_t io = 0;
+        auto up = [&](const auto &v) -> const void * {
+            io = (io + 15) / 16 * 16;
+            void *d = ip + io;
+            if (!v.empty()) (void)hipMemcpy(d, v.data(), bytes_of(v), hipMemcpyHostToDevice);
+            io += bytes_of(v);
+            return d;
+        };
+        ic.ncells[0] = (int)cellE.size();
+        ic.ncells[1] = (int)cellH.size();
+        ic.ptr[0] = up(rowE);
+        ic.ptr[1] = up(itE);
+        ic.ptr[2] = up(wE);
+        ic.ptr[3] = up(cellE);
+        ic.ptr[4] = up(mcE);
+        ic.ptr[5] = up(compE);
+        ic.ptr[6] = up(rowH);
+        ic.ptr[7] = up(itH);
+        ic.ptr[8] = up(wH);
+        ic.ptr[9] = up(cellH);
+        ic.ptr[10] = up(mcH);
+        ic.ptr[11] = up(compH);
+        HIP_OK(m, hipDeviceSynchronize());       // the host lists die with this block
+        ic.items_e = A.items_hstep;
+        ic.items_h = A.items_estep;
+        ic.w_e = A.w_hstep;
+        ic.w_h = A.w_estep;
+        ic.nsrc = nsrc;
+        ic.fstride = fstride;
+        ic.base = m->inj.p;
+        ic.valid = true;
+    }
     float *AF = (float *)m->adjf.p;
     float *Et[3] = {AF, AF + (size_t)nsrc * fstride, AF + (size_t)2 * nsrc * fstride};
     float *Hb[3] = {AF + (size_t)3 * nsrc * fstride, AF + (size_t)4 * nsrc * fstride, AF + (size_t)5 * nsrc * fstride};
     emm::InjectParams IE{}, IH{};
-    IE.ncells = (int)cellE.size();
+    IE.ncells = ic.ncells[0];
     IE.nf = A.nf;
-    IE.row = (const int *)up(rowE);
-    IE.item = (const int *)up(itE);
-    IE.w = (const float *)up(wE);
-    IE.cell = (const long long *)up(cellE);
-    IE.mcell = (const long long *)up(mcE);
-    IE.comp = (const int *)up(compE);
+    IE.row = (const int *)ic.ptr[0];
+    IE.item = (const int *)ic.ptr[1];
+    IE.w = (const float *)ic.ptr[2];
+    IE.cell = (const long long *)ic.ptr[3];
+    IE.mcell = (const long long *)ic.ptr[4];
+    IE.comp = (const int *)ic.ptr[5];
     IE.A = (const double2 *)m->injA.p;
     IE.phase = A.Ph.phase;                    // E stamps (n + 1) dt
     IE.F1 = Et[0];
@@ -2204,13 +2250,13 @@ emm_status gradient_run(emm_model *m, const emm_source *src, int nsrc, const emm
     IE.ce3 = m->ce[2];
     IE.scale_ce = 1;
     IH = IE;
-    IH.ncells = (int)cellH.size();
-    IH.row = (const int *)up(rowH);
-    IH.item = (const int *)up(itH);
-    IH.w = (const float *)up(wH);
-    IH.cell = (const long long *)up(cellH);
-    IH.mcell = (const long long *)up(mcH);
-    IH.comp = (const int *)up(compH);
+    IH.ncells = ic.ncells[1];
+    IH.row = (const int *)ic.ptr[6];
+    IH.item = (const int *)ic.ptr[7];
+    IH.w = (const float *)ic.ptr[8];
+    IH.cell = (const long long *)ic.ptr[9];
+    IH.mcell = (const long long *)ic.ptr[10];
+    IH.comp = (const int *)ic.ptr[11];
     IH.phase = A.Pe.phase;                    // H stamps (n + 1/2) dt
     IH.F1 = Hb[0];
     IH.F2 = Hb[1];
