@@ -247,3 +247,62 @@ def test_differentiation_48cube_central_differences(emm):
           f"vs oracle adjoint {rel_or.max():.2e}", flush=True)
     assert rel_or.max() <= CELL_TOL
     assert rel_fd.max() <= FD_TOL
+
+
+@pytest.mark.timeout(600)
+def test_large_marine_gradient_directional_derivative(emm):
+    """The 400 x 400 x 200 grid at 8th order with all 8 sources in one
+    gradient sweep, in the large-grid benchmark's launch configuration (58
+    planes per block, 32 x 8 tiles, source-slowest order, compact dt/eps,
+    compensated FP32 DTFT, 64-step graph replays) over 256 steps with a
+    25 Hz wavelet, for L = 1/2 sum |G|^2 (cotangent G, as the benchmark):
+    the GPU gradient summed against a smooth perturbation of log sigma in
+    the layer around the sources and the seafloor receivers (700-1100 m,
+    all x and y, so the padding and the CPML slabs are perturbed too; the
+    conductivity there is 1 S/m or more, so the fastest cell and dt do not
+    move) equals the derivative of L along it from GPU forwards of the
+    perturbed models (dt and the step count frozen).  A property that holds
+    at any size: the oracle's adjoint cannot run at this one.
+
+    L is far from linear over these steps: the ratio q(h) of the central
+    difference to the adjoint's prediction goes as 1 + c h^2 (measured
+    1.3e-2, 3.3e-3, 8.6e-4, 1.4e-4 at h = 1e-2, 5e-3, 2.5e-3, 1e-3), so the
+    test extrapolates (4 q(h) - q(2h)) / 3 from h = 2.5e-3 and 5e-3
+    (measured 1 + 3.3e-5) and bounds it at 2e-4; the FP32 rounding of the
+    forwards is below that at these h."""
+    nt, fp = 256, 25.0
+    w = configs.large_marine(nt=nt, rd=4, nsrc=8)
+    launch = dict(tile_kz=58, tile_x=32, src_order=1, nontemporal=0, ce_table=1, graph_steps=64,
+                  wavelet_fpeak=fp)
+    print(f"[gpu] large_marine gradient, 8 sources, {nt} steps", flush=True)
+    with emm.Model(w, **launch) as m:
+        G = m.forward()
+        dt = m.info()["dt"]
+        g, G2, _ = m.gradient(g_bar=G)
+    assert np.array_equal(G, G2)
+    z = w.x3.astype(np.float64)
+    bump = np.where((z >= 700.0) & (z <= 1100.0), np.cos(np.pi * (z - 900.0) / 400.0) ** 2, 0.0)
+    rho0 = [w.rho11, w.rho22, w.rho33]
+    assert max(float(r[bump > 0].max()) for r in rho0) <= 1.0
+
+    def misfit(t):
+        rho = [np.float32(r * np.exp(-t * bump)[:, None, None]) for r in rho0]
+        print(f"[gpu] large_marine forward, log sigma + {t:+.1e} bump", flush=True)
+        with emm.Model(w.with_(rho11=rho[0], rho22=rho[1], rho33=rho[2]), dt_override=dt,
+                       **launch) as mp:
+            assert mp.info()["dt"] == dt
+            Gp = mp.forward()
+        return 0.5 * np.sum(np.abs(Gp) ** 2), [-np.log(r.astype(np.float64)) for r in rho]
+
+    q = {}
+    for h in (2.5e-3, 5e-3):
+        (Lp, sp), (Lm, sm) = misfit(h), misfit(-h)
+        # g times the difference of log sigma that the two float32 models hold
+        dd = sum(float(np.sum(g[c] * (sp[c] - sm[c]))) for c in range(3))
+        q[h] = (Lp - Lm) / dd
+        print(f"[adjoint] large_marine 8 sources, h {h:.1e}: central difference {Lp - Lm:.6e}, "
+              f"gradient . perturbation {dd:.6e}, ratio - 1 {q[h] - 1.0:.3e}", flush=True)
+    qr = (4.0 * q[2.5e-3] - q[5e-3]) / 3.0
+    print(f"[adjoint] large_marine 8 sources: extrapolated ratio - 1 {qr - 1.0:.3e}", flush=True)
+    assert abs(q[2.5e-3] - 1.0) <= 2e-3
+    assert abs(qr - 1.0) <= 2e-4
