@@ -223,7 +223,8 @@ emm_status emm_query(const emm_model *m, emm_info *info);
  * Ex, Ey, Ez, Hx, Hy, Hz; the order of the paper's output listing,
  * Section 5): G^EE in V/(A m^2) for E channels, G^HE in 1/m^2 for H
  * channels.  green must hold 2*nsrc*nrec*popcount(chan_mask)*nfreq doubles;
- * any number nfreq >= 1 of frequencies (Section 3.5: one DTFT each).
+ * nsrc >= 1 and nrec >= 1 (else ARG), any number nfreq >= 1 of frequencies
+ * (Section 3.5: one DTFT each; else FREQ).
  * hip_stream: a hipStream_t to run on, or NULL for the library's own stream.
  * Errors: ARG, GEOMETRY, FREQ, NONFINITE, OOM, DEVICE. */
 emm_status emm_forward(emm_model *m, const emm_source *src, int nsrc,

@@ -387,6 +387,16 @@ def test_error_paths_on_device(emm):
         with pytest.raises(emm.EmmError) as e:
             m.forward(chan_mask=0)
         assert e.value.status == -1
+        # empty acquisitions: no receiver, no source, no frequency
+        with pytest.raises(emm.EmmError) as e:
+            m.forward(receivers=np.zeros((0, 3)))
+        assert e.value.status == -1
+        with pytest.raises(emm.EmmError) as e:
+            m.forward(sources=np.zeros((0, 3)), src_comp=np.zeros(0, dtype=np.int32))
+        assert e.value.status == -1
+        with pytest.raises(emm.EmmError) as e:
+            m.forward(freqs=np.zeros(0))
+        assert e.value.status == -5
         G = m.forward()                     # the model is still usable
         assert np.all(np.isfinite(G))
     # an unstable time step (forced from the host) ends non-finite, reported as such
