@@ -37,22 +37,21 @@ SHALLOW_GOLDEN = os.path.join(ROOT, "tests", "golden", "shallow_marine_air_oracl
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE (x 2.0) and WRITE_SIZE
 # (x 1.0), the factors from a 1 GiB copy kernel, keyed by workload, kernel and
 # launch configuration (tile width, rows per wavefront, source order,
-# nontemporal hint, compact dt/eps, sources; the z chunk length, which the
-# autotuner varies between runs, moves it by the queue prologue of the chunk,
-# (2r - 1)/kz of two arrays, ~1 % here).  A run whose autotuned launch
-# differs reports null: the counters belong to the kernel as profiled.
+# nontemporal hint, compact dt/eps, sources, z planes per block).  A run whose
+# autotuned launch differs reports null: the counters belong to the kernel as
+# profiled.
 TRAFFIC_KIB = {
-    # (workload, kernel, tx, ry, source order, nontemporal, compact, nsrc):
+    # (workload, kernel, tx, ry, source order, nontemporal, compact, nsrc, kz):
     #     (FETCH_SIZE KiB, WRITE_SIZE KiB); the large grid at 8th order with 8
-    #     sources, 58 z planes per block (profiles/step_kernel_large_marine_*)
-    ("large_marine_400x400x200", "e_step", 32, 1, 1, 0, 1, 8): (6401647.6, 4453677.2),
-    ("large_marine_400x400x200", "h_step", 32, 1, 1, 0, 1, 8): (5792745.6, 4453299.9),
-    ("large_marine_400x400x200", "e_step", 64, 1, 1, 0, 1, 8): (6574432.7, 4450545.0),
-    ("large_marine_400x400x200", "h_step", 64, 1, 1, 0, 1, 8): (5874936.8, 4454413.7),
-    ("large_marine_400x400x200", "e_step", 32, 1, 1, 1, 1, 8): (5845896.3, 4449371.8),
-    ("large_marine_400x400x200", "h_step", 32, 1, 1, 1, 1, 8): (5187237.2, 4451036.2),
-    ("large_marine_400x400x200", "e_step", 64, 1, 1, 1, 1, 8): (5762863.4, 4433150.8),
-    ("large_marine_400x400x200", "h_step", 64, 1, 1, 1, 1, 8): (5067565.9, 4436068.8),
+    #     sources (profiles/step_kernel_large_marine_*)
+    ("large_marine_400x400x200", "e_step", 32, 1, 1, 0, 1, 8, 58): (6401647.6, 4453677.2),
+    ("large_marine_400x400x200", "h_step", 32, 1, 1, 0, 1, 8, 58): (5792745.6, 4453299.9),
+    ("large_marine_400x400x200", "e_step", 64, 1, 1, 0, 1, 8, 58): (6574432.7, 4450545.0),
+    ("large_marine_400x400x200", "h_step", 64, 1, 1, 0, 1, 8, 58): (5874936.8, 4454413.7),
+    ("large_marine_400x400x200", "e_step", 32, 1, 1, 1, 1, 8, 58): (5845896.3, 4449371.8),
+    ("large_marine_400x400x200", "h_step", 32, 1, 1, 1, 1, 8, 58): (5187237.2, 4451036.2),
+    ("large_marine_400x400x200", "e_step", 64, 1, 1, 1, 1, 8, 58): (5762863.4, 4433150.8),
+    ("large_marine_400x400x200", "h_step", 64, 1, 1, 1, 1, 8, 58): (5067565.9, 4436068.8),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -153,7 +152,7 @@ def kernel_bytes(info, nsrc):
 
 def traffic(workload, kernel, info, nsrc):
     key = (workload, kernel, info["tile_x"], info["tile_rows"], info["src_order"],
-           info["nontemporal"], info["ce_table"], nsrc)
+           info["nontemporal"], info["ce_table"], nsrc, info["tile_kz"])
     kib = TRAFFIC_KIB.get(key)
     if kib is None:
         return None
@@ -213,13 +212,32 @@ def large_batched(emm, w, window, t_batched_fwd):
     import numpy as np
     nsrc = len(w.sources)
     out = {"sources": nsrc, "time_steps": window, "batched_forward_s": t_batched_fwd}
-    with emm.Model(w, tile_kz=-1, graph_steps=64) as m:
+    with emm.Model(w, tile_kz=-1, graph_steps=64, profile=1) as m:
         m.forward(sources=w.sources[:1], src_comp=w.src_comp[:1])        # tune for 1 + warm
         t = time.perf_counter()
-        plain = [m.forward(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1])
-                 for s in range(nsrc)]
+        plain, k = [], dict(e_ms=0.0, h_ms=0.0, e_n=0, h_n=0)
+        for s in range(nsrc):
+            plain.append(m.forward(sources=w.sources[s:s + 1], src_comp=w.src_comp[s:s + 1]))
+            i1 = m.info()
+            for a, b in (("e_ms", "e_kernel_ms"), ("h_ms", "h_kernel_ms"), ("e_n", "e_launches"),
+                         ("h_n", "h_launches")):
+                k[a] += i1[b]
         out["plain_forward_loop_s"] = time.perf_counter() - t
         log(f"[bench] large: plain forward loop {out['plain_forward_loop_s']:.2f} s")
+        # the one-source kernels of that loop against the peak (section-8(d)
+        # bytes of one source: its dt/eps counted in full)
+        kb1 = kernel_bytes(i1, 1)
+        one = {"launch": {q: i1[q] for q in ("tile_kz", "tile_x", "tile_rows", "src_order",
+                                              "nontemporal", "ce_table")}}
+        for name, nb, ms, n in (("e_step", kb1["e_8d"], k["e_ms"], k["e_n"]),
+                                ("h_step", kb1["h"], k["h_ms"], k["h_n"])):
+            us = ms / max(n, 1) * 1e3
+            one[name] = {"bytes_per_launch": nb, "avg_launch_us": us, "launches_timed": n,
+                         "achieved_GBs": nb / us / 1e3, "frac": nb / us / 1e3 / HBM_PEAK_GBS}
+        out["one_source_kernels"] = one
+        log(f"[bench] large: one-source E/H {one['e_step']['avg_launch_us']:.1f}/"
+            f"{one['h_step']['avg_launch_us']:.1f} us (frac {one['e_step']['frac']:.3f}/"
+            f"{one['h_step']['frac']:.3f}), {one['launch']}")
         Gb = m.forward()
         out["batched_equals_plain_bitwise"] = bool(np.array_equal(Gb, np.concatenate(plain, 0)))
         # warm (buffers of the one-source plan) on the last source, so that the

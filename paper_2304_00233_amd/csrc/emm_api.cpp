@@ -1704,14 +1704,16 @@ emm_status autotune(emm_model *m, hipStream_t stream) {
     Acq &A = m->acq;
     if (m->opt.tile_kz >= 0 || m->tuned.count(A.nsrc)) return EMM_OK;
     const int nzv = z_planes(m);
-    // every distinct z chunking with 3..64 planes per block (the smallest kz
-    // of each chunk count): how many waves of blocks a launch needs on the
-    // chip moves the time by several per cent between neighbouring kz
+    // every distinct z chunking with at least 3 planes per block (the
+    // smallest kz of each chunk count): how many waves of blocks a launch
+    // needs on the chip moves the time by several per cent between
+    // neighbouring kz, and on deep grids one to three chunks per column
+    // save the z-queue refills of the others
     std::vector<int> cand;
     for (int zc = 1; zc <= nzv; ++zc) {
         const int kz = (nzv + zc - 1) / zc;
         if (kz < 3) break;
-        if (kz <= 64 && (cand.empty() || cand.back() != kz)) cand.push_back(kz);
+        if (cand.empty() || cand.back() != kz) cand.push_back(kz);
     }
     if (std::find(cand.begin(), cand.end(), A.Pe.kz) == cand.end()) cand.push_back(A.Pe.kz);
     std::vector<int> hints = {0, 1}, compacts = {0};
