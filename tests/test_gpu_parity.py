@@ -109,11 +109,14 @@ def test_bitwise_determinism_runs_and_tiles(emm, rd):
     G7, i7 = _run(emm, w, tile_rows=2, ce_table=1, tile_kz=5)
     G8, i8 = _run(emm, w, tile_rows=4, ce_table=0, nontemporal=1)
     G9, i9 = _run(emm, w, tile_rows=4, ce_table=1)
+    # one z chunk per column (a request beyond the depth is clamped to it)
+    G10, i10 = _run(emm, w, tile_kz=1000, tile_x=32)
+    assert i10["tile_kz"] == i10["n3pad"] - 2 * rd
     assert i3["tile_kz"] == 3 and (i4["tile_x"], i5["tile_x"], i6["tile_x"]) == (32, 64, 32)
     assert (i4["ce_table"], i5["ce_table"], i6["ce_table"]) == (1, 0, 0)
     assert (i7["tile_rows"], i8["tile_rows"], i9["tile_rows"]) == (2, 4, 4)
     assert (i7["tile_x"], i8["tile_x"], i9["tile_x"]) == (64, 64, 64)
-    for G in (G2, G3, G4, G5, G6, G7, G8, G9):
+    for G in (G2, G3, G4, G5, G6, G7, G8, G9, G10):
         assert np.array_equal(G1, G)
 
 
