@@ -498,7 +498,9 @@ def main():
     log(f"[bench] workload {w.name} padded cells {w.padded_cells} sources {nsrc}")
     if args.gradient_sample:
         w = w.with_(nt=args.gradient_sample)
-        with emm.Model(w, tile_kz=args.tile_kz, graph_steps=args.graph) as m:
+        with emm.Model(w, tile_kz=args.tile_kz, graph_steps=args.graph, tile_x=args.tile_x,
+                       tile_rows=args.tile_rows, src_order=args.src_order,
+                       nontemporal=args.nontemporal) as m:
             G = m.forward()
             m.gradient(g_bar=G)          # sizes the checkpoint buffers
             m.forward()                  # leaves no checkpoints: the timed call runs its forward
