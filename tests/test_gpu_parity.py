@@ -52,15 +52,8 @@ def _check(emm, w, label, **opt):
     return G_g, G_o, rep
 
 
-def _plain_with_offaxis():
-    w = configs.plain_forward()
-    xs = np.array([-1800.0, -1200.0, -600.0, 600.0, 1200.0, 1800.0])
-    off = np.stack([xs, np.full_like(xs, 450.0), np.full_like(xs, -350.0)], axis=1)
-    return w.with_(receivers=np.concatenate([w.receivers, off]))
-
-
 def test_plain_forward_48cube(emm):
-    w = _plain_with_offaxis()
+    w = configs.plain_forward_offaxis()
     G_g, _, _ = _check(emm, w, "plain_forward_48cube")
     # the GPU result is also close to the analytic whole-space dipole
     rec = w.receivers[21:]

@@ -98,6 +98,17 @@ def plain_forward(nt: int = 0) -> Workload:
                     freqs=np.array([1.0]), rd=2, nb=10, ne=7, f0=1.0, nt=nt)
 
 
+def plain_forward_offaxis(nt: int = 0) -> Workload:
+    """The plain-forward model with 6 receivers off the source's axis
+    (y = 450 m, z = -350 m) after the 21 inline ones: on the axis the
+    magnetic field and the transverse E components vanish, so the off-axis
+    receivers carry the channels that a comparison can hold to a tolerance."""
+    w = plain_forward(nt)
+    xs = np.array([-1800.0, -1200.0, -600.0, 600.0, 1200.0, 1800.0])
+    off = np.stack([xs, np.full_like(xs, 450.0), np.full_like(xs, -350.0)], axis=1)
+    return w.with_(receivers=np.concatenate([w.receivers, off]))
+
+
 # --------------------------------------------------------------------------
 # Marine layered: 128 x 128 x 96 nodes, 100 m horizontal; z positive down,
 # sea surface at 0, seafloor node at 1000 m with 25 m spacing, geometric
