@@ -164,10 +164,12 @@ def timed_forwards(m, steps, warmup, label):
     for i in range(warmup):
         m.forward()
         log(f"[bench] {label} warmup {i} done")
-    acc = dict(e_ms=0.0, h_ms=0.0, e_n=0, h_n=0, dev_ms=0.0)
+    acc = dict(e_ms=0.0, h_ms=0.0, e_n=0, h_n=0, dev_ms=0.0, walls=[])
     t0 = time.perf_counter()
     for i in range(steps):
+        t1 = time.perf_counter()
         m.forward()
+        acc["walls"].append(time.perf_counter() - t1)
         inf = m.info()
         acc["e_ms"] += inf["e_kernel_ms"]
         acc["h_ms"] += inf["h_kernel_ms"]
@@ -555,10 +557,12 @@ def main():
             f"(inner {i['ckpt_inner']}), sources per sweep {i['src_group']}")
         return
 
+    t_create = time.perf_counter()
     model = emm.Model(w, profile=1, graph_steps=args.graph, tile_kz=args.tile_kz, fused=args.fused,
                       tile_x=args.tile_x, tile_rows=args.tile_rows, src_order=args.src_order,
                       **({"airwave": args.air_transform} if w.airwave else {}),
                       nontemporal=args.nontemporal)
+    create_s = time.perf_counter() - t_create
     wall, acc, info = timed_forwards(model, args.steps, args.warmup, "main")
     model.close()
     nt = info["nt"]
@@ -605,6 +609,12 @@ def main():
                      "launches_timed": acc["e_n"]},
         "interior_gcell_step_per_s": (len(w.x1) * len(w.x2) * len(w.x3)) * nt * nsrc * args.steps / wall / 1e9,
         "device_loop_ms_per_step": acc["dev_ms"] / args.steps,
+        "ms_per_step_median": float(sorted(acc["walls"])[len(acc["walls"]) // 2] * 1e3),
+        # set-up, outside the timed region: emm_create (padded grid, FD tables,
+        # dt/eps, device allocation and upload of the model), and the host
+        # share of each forward (acquisition tables, launches, read-back)
+        "setup": {"model_create_s": create_s,
+                  "per_forward_host_ms": (wall - acc["dev_ms"] / 1e3) / args.steps * 1e3},
         "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"], "tile_rows": info["tile_rows"],
                    **({"air_transform": ("hipfft", "direct")[info["air_transform"] - 1]}
                       if info["air_transform"] else {}),
