@@ -626,9 +626,16 @@ def main():
                          "achieved_GBs": kb["h"] / h_avg_s / 1e9,
                          "frac": kb["h"] / h_avg_s / 1e9 / HBM_PEAK_GBS,
                          "traffic": traffic(w.name, "h_step", info, nsrc)}
+    # the counter traffic per launch as a rate against both peaks
+    tr = out["roofline"]["traffic"]
+    if tr:
+        out["roofline"]["traffic_GBs"] = tr / e_avg_s / 1e9
+        out["roofline"]["traffic_frac"] = tr / e_avg_s / 1e9 / HBM_PEAK_GBS
     if stream_ref:
         out["stream_reference"] = dict(stream_ref)
         out["stream_reference"]["e_step_frac_of_it"] = achieved / stream_ref["GBs"]
+        if tr:
+            out["stream_reference"]["e_step_traffic_frac_of_it"] = tr / e_avg_s / 1e9 / stream_ref["GBs"]
     if large and not args.quick:
         log("[bench] batched forward + gradient legs")
         out["batched"] = large_batched(emm, w, nt, ms_per_step / 1e3)
