@@ -1,7 +1,7 @@
 """The air boundary above the sea surface (Section 3.3) on the GPU, through
 the C ABI, against the FP64 oracle (whose ghost fills are pinned in
-tests/test_oracle_airwave.py): small ragged cases at r = 2 and r = 4 (1
-and 3 E ghost planes, 2 and 4 H ghost half planes), several sources in one
+tests/test_oracle_airwave.py): small ragged cases at r = 1 to 4 (r - 1 E
+ghost planes, r H ghost half planes), several sources in one
 launch bitwise equal to one at a time, with either form of the ghost-fill
 transforms (hipFFT or the direct kernels), the entry points that
 refuse the air boundary, and the full-size shallow-water workload against
@@ -32,16 +32,17 @@ def _air_case(seed, shape, rd, nb, nsrc=1, nt=500):
 
 
 # the ghost-fill transforms: 2 = hipFFT, 3 = the direct kernels (planes up
-# to 1024 points per axis, each split once as n = f m; the padded planes
+# to 512 points per axis, each split once as n = f m; the padded planes
 # here: 57 x 49 = (3 x 19) x (7 x 7), 52 x 49 = (4 x 13) x (7 x 7),
-# 40 x 84 = (5 x 8) x (7 x 12) and 46 x 44 = (2 x 23) x (4 x 11))
+# 40 x 84 = (5 x 8) x (7 x 12), 46 x 44 = (2 x 23) x (4 x 11) and, at
+# r = 3, 52 x 47 = (4 x 13) x 47 (prime: whole-line sums))
 AIR = [2, 3]
 
 
 @pytest.mark.parametrize("air", AIR, ids=["fft", "direct"])
 @pytest.mark.parametrize("seed,shape,rd,nb", [(50, (37, 29, 23), 2, 6), (51, (30, 27, 25), 4, 5),
-                                              (52, (26, 70, 19), 1, 4)],
-                         ids=["r2", "r4", "r1_ragged"])
+                                              (52, (26, 70, 19), 1, 4), (53, (32, 27, 24), 3, 5)],
+                         ids=["r2", "r4", "r1_ragged", "r3"])
 def test_air_boundary_matches_oracle(emm, seed, shape, rd, nb, air):
     w = _air_case(seed, shape, rd, nb)
     G_o, info_o = F.forward(w)
