@@ -48,3 +48,55 @@ def test_random_case_matches_oracle(emm, i):
     rep = compare(G_g, G_o, w.channels)
     print(f"[parity] random case {i}: {rep}", flush=True)
     assert rep["ok"], rep
+
+
+def _draw_gradient(i):
+    rng = np.random.default_rng(20360 + i)
+    rd = int(rng.integers(1, 5))
+    nsrc = int(rng.integers(1, 3))
+    w = configs.small_case(
+        seed=400 + i, shape=tuple(int(v) for v in rng.integers(14, 30, 3)), rd=rd,
+        nb=int(rng.choice([0, 3, 5])), ne=rd + 1, nt=int(rng.integers(250, 401)),
+        nu_axes=(False, True, True), nsrc=nsrc, nrec=5, freqs=(0.5, 1.5),
+        src_comp=tuple(int(c) for c in rng.integers(0, 3, nsrc)))
+    opt = dict(tile_x=int(rng.choice([32, 64])), checkpoint_every=int(rng.choice([0, 23, 50])))
+    return w, opt
+
+
+@pytest.mark.parametrize("i", range(6))
+def test_random_gradient_matches_oracle(emm, i):
+    """The misfit gradient of seeded random cases (data from the model with
+    every resistivity times 1.3) against the oracle's adjoint: relative L2
+    within 1e-4, or within three times the gradient's own FP32 rounding
+    noise where that is larger.  The noise is the larger change of the GPU
+    gradient when every resistivity is nudged by +2^-20 or -2^-20 (exact
+    changes of ~1e-6; one nudge alone can land an order of magnitude under
+    the noise: 1.2e-5 and 1.2e-4 on case 4).  A draw whose noise exceeds
+    1e-2 is skipped, since no comparison can hold it (case 5: 0.19)."""
+    w, opt = _draw_gradient(i)
+    print(f"[gpu] random gradient case {i}: {w.name} nb={w.nb} sources={len(w.sources)} {opt}",
+          flush=True)
+    s = np.float32(1.3)
+    st = F.make_setup(w, 2.0 * np.sqrt(max(w.freqs)))
+    G_obs, _ = F.forward(w.with_(rho11=w.rho11 * s, rho22=w.rho22 * s, rho33=w.rho33 * s),
+                         dt_override=st.dt)
+    chi_o, g_o, _ = F.misfit_gradient(w, G_obs, frozen=st)
+    with emm.Model(w, **opt) as m:
+        dt = m.info()["dt"]
+        g, _, chi = m.gradient(g_obs=G_obs)
+    noise = 0.0
+    for e in (1.0 + 2.0 ** -20, 1.0 - 2.0 ** -20):
+        e = np.float32(e)
+        with emm.Model(w.with_(rho11=w.rho11 * e, rho22=w.rho22 * e, rho33=w.rho33 * e),
+                       dt_override=dt, **opt) as m:
+            gn, _, _ = m.gradient(g_obs=G_obs)
+        noise = max(noise, np.linalg.norm(gn - g) / np.linalg.norm(g))
+    err = np.linalg.norm(g - g_o) / np.linalg.norm(g_o)
+    print(f"[adjoint] random case {i}: rel L2 {err:.2e}, rounding noise {noise:.2e}, "
+          f"chi {chi:.6e} oracle {chi_o:.6e}", flush=True)
+    if noise > 1e-2:
+        pytest.skip(f"ill-conditioned draw: FP32 rounding noise of the gradient {noise:.1e}")
+    # chi sums |log(G/G_obs)|^2 over data down to ~1e-7 of the largest |G|
+    # (FP32 fields): 1.3e-4 relative on case 0
+    assert chi == pytest.approx(chi_o, rel=1e-3)
+    assert err <= max(1e-4, 3.0 * noise)
