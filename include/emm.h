@@ -328,7 +328,10 @@ emm_status emm_forward_batch(const emm_job *jobs, int njobs, int graph_steps, vo
  * checkpoint_every > 0, or an emm_gradient, whose own forward stores them),
  * they are reused and only the reverse sweep runs; otherwise the forward is
  * run here.  The sum over sources and the fold of the padding onto the
- * input cells run on the device.
+ * input cells run on the device.  The fields are FP32: a log misfit over
+ * data far below the largest |G| (near the fields' rounding) amplifies that
+ * rounding into the gradient; floor or down-weight such data and pass the
+ * cotangent as g_bar.
  * This is the gradient that CSEM inversion needs (the paper's stated
  * horizon, Section 9).  Errors: as emm_forward, plus ARG. */
 emm_status emm_gradient(emm_model *m, const emm_source *src, int nsrc,
