@@ -3,7 +3,8 @@ grid sizes, stencil order, CPML thickness, stretched axes, sources (count
 and dipole direction), receivers, frequencies and the launch options (tile
 width, z chunk, compact dt/eps, nontemporal hints, source order, graph
 replays, DTFT accumulators) drawn together, so that combinations no
-hand-written case names still meet the tolerance."""
+hand-written case names still meet the tolerance: forwards, misfit
+gradients and forwards with the air boundary."""
 import numpy as np
 import pytest
 
@@ -100,3 +101,33 @@ def test_random_gradient_matches_oracle(emm, i):
     # (FP32 fields): 1.3e-4 relative on case 0
     assert chi == pytest.approx(chi_o, rel=1e-3)
     assert err <= max(1e-4, 3.0 * noise)
+
+
+def _draw_air(i):
+    rng = np.random.default_rng(20460 + i)
+    rd = int(rng.integers(1, 5))
+    nsrc = int(rng.integers(1, 3))
+    w = configs.small_case(
+        seed=500 + i, shape=tuple(int(v) for v in rng.integers(16, 40, 3)), rd=rd,
+        nb=int(rng.choice([3, 5, 6])), ne=rd + 2, nt=int(rng.integers(300, 501)),
+        nu_axes=(False, False, bool(rng.integers(0, 2))), nsrc=nsrc, nrec=int(rng.integers(3, 8)),
+        freqs=tuple(np.sort(np.exp(rng.uniform(np.log(0.3), np.log(2.0), int(rng.integers(1, 4)))))),
+        src_comp=tuple(int(c) for c in rng.integers(0, 3, nsrc))).with_(airwave=True)
+    opt = dict(airwave=int(rng.choice([2, 3])), tile_x=int(rng.choice([32, 64])),
+               graph_steps=int(rng.choice([0, 16])), src_order=int(rng.integers(0, 2)))
+    return w, opt
+
+
+@pytest.mark.parametrize("i", range(4))
+def test_random_air_case_matches_oracle(emm, i):
+    """Seeded random cases with the air boundary (either ghost-fill
+    transform) against the oracle."""
+    w, opt = _draw_air(i)
+    print(f"[gpu] random air case {i}: {w.name} nb={w.nb} sources={len(w.sources)} "
+          f"comp={list(w.src_comp)} freqs={len(w.freqs)} {opt}", flush=True)
+    G_o, info_o = F.forward(w)
+    G_g, info_g = emm.forward_workload(w, **opt)
+    assert info_g["dt"] == pytest.approx(info_o["dt"], rel=1e-12)
+    rep = compare(G_g, G_o, w.channels)
+    print(f"[parity] random air case {i}: {rep}", flush=True)
+    assert rep["ok"], rep
