@@ -610,9 +610,10 @@ def main():
         "interior_gcell_step_per_s": (len(w.x1) * len(w.x2) * len(w.x3)) * nt * nsrc * args.steps / wall / 1e9,
         "device_loop_ms_per_step": acc["dev_ms"] / args.steps,
         "ms_per_step_median": float(sorted(acc["walls"])[len(acc["walls"]) // 2] * 1e3),
-        # set-up, outside the timed region: emm_create (padded grid, FD tables,
-        # dt/eps, device allocation and upload of the model), and the host
-        # share of each forward (acquisition tables, launches, read-back)
+        # set-up: emm_create (padded grid, FD tables, dt/eps, device
+        # allocation and upload of the model; outside the timed region), and
+        # the host share of each forward (acquisition tables, launches,
+        # read-back; inside it)
         "setup": {"model_create_s": create_s,
                   "per_forward_host_ms": (wall - acc["dev_ms"] / 1e3) / args.steps * 1e3},
         "launch": {"tile_kz": info["tile_kz"], "tile_x": info["tile_x"], "tile_rows": info["tile_rows"],
