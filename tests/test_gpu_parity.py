@@ -435,3 +435,28 @@ def test_graph_replays_are_bitwise_identical(emm):
         G1 = m.forward()
         G2 = m.forward()
     assert np.array_equal(G0, G1) and np.array_equal(G0, G2)
+
+
+def test_roofline_bytes_follow_the_algorithmic_count(emm):
+    """The bytes the roofline divides by: per launch of one source, the E step
+    reads H and E and writes E (36 B per padded cell) plus dt/eps (12 B as
+    three FP32 arrays, 4 B in the compact form), the H step 36 B, both + 16 B
+    per CPML slab cell per axis (two memory variables read and written);
+    for S sources the benchmark's count reads the FP32 dt/eps once:
+    (36 S + 12) N and 36 S N.  Recomputed here from the padded grid."""
+    import bench
+    w = configs.small_case(seed=16, shape=(27, 23, 21), nb=6, nsrc=3, nt=40)
+    for ce in (0, 1):
+        _, info = _run(emm, w, ce_table=ce)
+        n = (info["n1pad"], info["n2pad"], info["n3pad"])
+        N = float(n[0] * n[1] * n[2])
+        ncpml = sum(2.0 * w.nb * N / na for na in n)
+        assert info["ce_table"] == ce
+        assert info["cells"] == N
+        assert info["e_bytes"] == (40.0 if ce else 48.0) * N + 16.0 * ncpml
+        assert info["h_bytes"] == 36.0 * N + 16.0 * ncpml
+        kb = bench.kernel_bytes(info, 3)
+        assert kb["e_8d"] == pytest.approx((36.0 * 3 + 12.0) * N + 16.0 * 3 * ncpml, rel=1e-12)
+        assert kb["e_moved"] == pytest.approx((36.0 * 3 + (4.0 if ce else 12.0)) * N + 16.0 * 3 * ncpml,
+                                              rel=1e-12)
+        assert kb["h"] == pytest.approx(3 * (36.0 * N + 16.0 * ncpml), rel=1e-12)
