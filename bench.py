@@ -499,9 +499,9 @@ def main():
         log(f"[bench] copied {a.numel() * 4} bytes")
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): nothing in this build "
-              "runs on a second GPU; the path would shard by source with no communication "
-              "between GPUs", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs on one "
+              "device; the path would shard by source with no communication between GPUs",
+              file=sys.stderr)
         sys.exit(2)
 
     # the streaming reference runs in a child process before this one touches
