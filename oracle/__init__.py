@@ -21,7 +21,10 @@ staggered derivative (appendix on dispersion), the CFL closed form, the
 analytic whole-space electric dipole (also on a strongly stretched z axis,
 which pins the injection control volume and the padding), the z-domain
 identity solved by a sparse direct solver, reciprocity (also on the marine
-stretched axis with CPML), omega0- and wavelet-invariance, CPML reflection.
+stretched axis with CPML), omega0- and wavelet-invariance, CPML reflection;
+the discrete adjoint by central differences of the forward; the air
+boundary's ghost fills by exact harmonic and potential fields and by the
+z-domain solve with the fills as operators; the convergence stop.
 Layered and blocky models are pinned as discrete operators (the z-domain
 identity holds for any model); their discretisation error against the
 continuous layered-earth solution is not measured (no layered-earth solver
